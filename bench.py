@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the hopping-matrix hot path on one MI355X; prints one JSON line.
+
+Workload (default ``qtm32``): 32^3x64 lattice, Haar-random SU(3) links, a
+Gaussian odd source, kappa = 0.1632, 2 kappa mu = 0.0013, antiperiodic time.
+One step = one complete FP64 CG solve on Qhat^dagger Qhat to a 1e-10 true
+relative residual (every hopping-matrix and twisted-mass application, BLAS-1
+update and reduction of the path), with the inputs resident in HBM.
+
+value = Dslash GFlop/s over the timed steps: 1320 flop per output site per
+hopping-matrix application, times the applications the solves made, over the
+wall time of the steps.  The roofline entry is for the dominant kernel, the
+FP64 hopping matrix storing A^-1 H_eo p (1536 algorithmic bytes per site),
+timed live with HIP events on the stream it runs on.  The mixed-precision
+(FP32 inner) defect-correction solve of the same system is timed beside it,
+and the CPU oracle is timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Dslash GFlop/s + % HBM roofline at 32^3x64; mixed vs FP64 CG time to 1e-10"
+FLOP_PER_SITE = 1320
+BYTES_PER_SITE_F64 = 1536          # 8 links x 144 B + input spinor 192 B + output 192 B
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_f64_32x32x32x64_traffic.json")
+HOP_SOURCES = [os.path.join(ROOT, "paper_1311_4521_amd", "csrc", f)
+               for f in ("hop.hip", "common.h", "kernels.h")]
+
+WORKLOADS = {
+    "qtm32": dict(dims=(64, 32, 32, 32), kappa=0.1632, mt=0.0013, seed=2,
+                  label="Qtm + FP64 CG to 1e-10 on 32^3x64, Haar SU(3) links, "
+                        "kappa=0.1632, 2*kappa*mu=0.0013, antiperiodic time"),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def hop_source_hash():
+    h = hashlib.sha256()
+    for f in HOP_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_sites):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None if absent or taken on other code."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != hop_source_hash() or t.get("sites") != n_sites:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(dims, U, psi, kappa, theta, budget_s):
+    import oracle
+    Vh = len(psi)
+    t0 = time.perf_counter()
+    oracle.hop(dims, "eo", U, psi, kappa, theta)
+    one = time.perf_counter() - t0
+    reps = max(1, int(budget_s / max(one, 1e-9)))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.hop(dims, "eo", U, psi, kappa, theta)
+    dt = time.perf_counter() - t0
+    return {
+        "value": round(FLOP_PER_SITE * Vh * reps / dt / 1e9, 3),
+        "unit": "GFlop/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{reps} oracle D_eo applications on the {'x'.join(map(str, dims))} fields "
+                  f"({Vh} output sites each, {dt:.1f} s)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="qtm32", choices=sorted(WORKLOADS))
+    ap.add_argument("--mixed-steps", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md for how the lattice would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import fieldgen
+    import paper_1311_4521_amd as tm
+    from paper_1311_4521_amd import tmhop
+
+    w = WORKLOADS[args.workload]
+    dims, kappa, mt = w["dims"], w["kappa"], w["mt"]
+    mu = mt / (2 * kappa)
+    theta = (1.0, 0.0, 0.0, 0.0)
+    torch.cuda.set_device(0)
+
+    log(f"generating fields {dims} (seed {w['seed']})")
+    U = fieldgen.gauge_haar(dims, w["seed"])
+    Vh = int(np.prod(dims)) // 2
+    b = fieldgen.spinor_gauss(Vh, 100 + w["seed"])
+
+    lat = tm.Lattice(dims, 0)
+    G = tm.gauge_import(lat, U)
+    tb = tm.spinor_import(lat, b)
+    x = lat.new_spinor()
+    log("fields resident on the device")
+
+    def solve(inner):
+        x.zero_()
+        return tm.cg_solve(lat, x, tb, G, kappa, mu, theta, 1e-10, 20000, inner)
+
+    for k in range(args.warmup):
+        it, res, ok = solve(tm.F64)
+        log(f"warmup {k}: {it} iterations, true residual {res:.3e}")
+
+    # ---- timed region: K full FP64 solves
+    tmhop.profile_enable(lat, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for k in range(args.steps):
+        it, res, ok = solve(tm.F64)
+        iters.append(it)
+        if not ok:
+            raise SystemExit(f"FP64 CG did not converge (residual {res})")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    counts = [tmhop.profile_read(lat, k) for k in range(tmhop.PROFILE_KINDS)]
+    tmhop.profile_enable(lat, False)
+    log(f"timed {args.steps} FP64 solves: {dt * 1e3 / args.steps:.2f} ms each, {iters[0]} iterations")
+    x64 = x.clone()
+    res64 = res
+
+    n_hops = sum(c[0] for c in counts)
+    value = FLOP_PER_SITE * Vh * n_hops / dt / 1e9
+    n0, ms0 = counts[tmhop.profile_kind(tm.F64, 0)]
+    hop_us = ms0 * 1e3 / n0
+    achieved = BYTES_PER_SITE_F64 * Vh / (hop_us * 1e-6) / 1e9
+    per_kind = {}
+    names = ["f64_ainv_or_plain", "f64_twist", "f64_twist_norm", "f32_ainv_or_plain", "f32_twist",
+             "f32_twist_norm"]
+    for k, (n, ms) in enumerate(counts):
+        if n:
+            per_kind[names[k]] = {"launches": n, "avg_us": round(ms * 1e3 / n, 2)}
+
+    # ---- mixed precision beside it
+    mixed = []
+    mixed_it = mixed_res = None
+    for k in range(1 + args.mixed_steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        it, res, ok = solve(tm.F32)
+        torch.cuda.synchronize()
+        if not ok:
+            raise SystemExit(f"mixed CG did not converge (residual {res})")
+        if k > 0:
+            mixed.append(time.perf_counter() - t1)
+        mixed_it, mixed_res = it, res
+    mixed_ms = 1e3 * (sum(mixed) / len(mixed)) if mixed else None
+    d = (x - x64).double()
+    mixed_vs_fp64 = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(x64))
+    fp64_ms = dt * 1e3 / args.steps
+    log(f"mixed solve: {mixed_ms:.2f} ms, {mixed_it} inner iterations")
+
+    traffic = measured_traffic(Vh)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GFlop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(fp64_ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["label"], "dims_TXYZ": list(dims), "kappa": kappa,
+                   "two_kappa_mu": mt, "tol": 1e-10, "seed": w["seed"]},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "kernel": "hop_kernel<double,0> (A^-1 H_eo store)",
+            "bytes_per_site": BYTES_PER_SITE_F64,
+            "avg_us": round(hop_us, 2),
+            "launches": n0,
+        },
+        "hop_gflops": round(FLOP_PER_SITE * Vh / (hop_us * 1e-6) / 1e9, 1),
+        "kernels": per_kind,
+        "cg_fp64": {"ms": round(fp64_ms, 3), "iterations": iters[0], "true_rel_res": res64},
+        "cg_mixed_f32": {"ms": round(mixed_ms, 3) if mixed_ms else None,
+                         "inner_iterations": mixed_it, "true_rel_res": mixed_res,
+                         "rel_diff_vs_fp64_solution": mixed_vs_fp64,
+                         "speedup_vs_fp64": round(fp64_ms / mixed_ms, 3) if mixed_ms else None},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        line["cpu_baseline"] = cpu_baseline(dims, U, b, kappa, theta, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    lat.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * tmhop.h -- C-ABI of libtmhop.so: the Wilson hopping matrix between the two
+ * checkerboards of a 4D lattice, the even-odd preconditioned twisted-mass
+ * operator built on it, and CG on that operator, on one MI355X (gfx950).
+ *
+ * The operation follows Deuzeman, Jansen, Kostrzewa, Urbach, "Experiences
+ * with OpenMP in tmLQCD" (LATTICE 2013): the hopping matrix Hopping_Matrix
+ * between even and odd sites (Section 2, "Optimizing the Hopping Matrix", and
+ * the introduction, which names the half-spinor and full-spinor bodies), the
+ * twisted-mass Wilson fermions it serves (introduction), and the real scalar
+ * product scalar_prod_r used by the inverter (Section 3, "Measuring and
+ * Reducing Overheads").  The paper does not write the operator down; this
+ * library takes the standard definitions:
+ *
+ *   lattice   Z_T x Z_LX x Z_LY x Z_LZ, dims = {T, LX, LY, LZ}, mu = 0..3 =
+ *             t,x,y,z; every extent even and >= 2.  lex = ((t*LX+x)*LY+y)*LZ+z,
+ *             parity = (t+x+y+z) mod 2 (0 = even).  A site's even-odd index is
+ *             lex >> 1 (its rank among the sites of its parity in lex order).
+ *   gammas    chiral basis: gamma_mu = [[0, e_mu], [e_mu^+, 0]] with e_0 = -1,
+ *             e_k = -i sigma_k, so gamma_5 = gamma_0 gamma_1 gamma_2 gamma_3 =
+ *             diag(1, 1, -1, -1).
+ *   hopping   (H psi)(x) = kappa sum_mu [ eta+_mu(x) (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                                       + eta-_mu(x) (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ *             eta+ = exp(+i pi theta_mu) if the forward hop wraps from L_mu-1
+ *             to 0, eta- = exp(-i pi theta_mu) if the backward hop wraps from
+ *             0 to L_mu-1, else 1.  theta = {1,0,0,0} is antiperiodic in time.
+ *             H_eo (TMH_EO) maps odd to even sites, H_oe (TMH_OE) even to odd.
+ *   twisted   mt = 2 kappa mu, A(s) = 1 + i s mt gamma_5 (s = +-1),
+ *   mass      Mhat(s) = A(s) - H_oe A(s)^-1 H_eo on odd fields,
+ *             Qhat(s) = gamma_5 Mhat(s); Qhat(+)^dagger = Qhat(-).
+ *   CG        solves Qhat(+)^dagger Qhat(+) x = b on odd fields.
+ *
+ * Memory and ownership.  Every field buffer is a device pointer owned by the
+ * caller (typically torch tensors on the device the lattice was created
+ * for); the library never keeps a pointer past the call.  The library owns
+ * only the lattice handle and its scratch (CG vectors, the intermediate even
+ * field, reduction partials and, for mixed precision, low-precision copies),
+ * allocated on first use and freed by tmh_lattice_destroy.
+ *
+ * Internal field layout ("site-coalesced structure of arrays").  S =
+ * tmh_site_stride() is Vh = V/2 rounded up to a multiple of 64.  A complex
+ * number is two reals (re, im) of the precision's real type: double for
+ * TMH_F64, float for TMH_F32.
+ *   spinor (one parity): component c = 3*spin + colour of site i is the
+ *             complex element c*S + i; tmh_spinor_bytes() = 12*S complexes.
+ *   gauge (whole lattice): element (a, b) of U_mu(x), x of parity p with
+ *             even-odd index i, is the complex element ((p*4+mu)*9 + 3a+b)*S + i;
+ *             tmh_gauge_bytes() = 72*S complexes.
+ * Elements i in [Vh, S) are padding: never read as data, never written by
+ * the operators.
+ *
+ * Canonical (import/export) layouts, FP64 complex interleaved, device memory:
+ *   gauge   [4][V][3][3]  (mu, lex, row, column)
+ *   spinor  [Vh][4][3]    (even-odd index, spin, colour) on one parity
+ *
+ * Streams.  Import, export, hop, qtm and the BLAS-1 calls enqueue on the
+ * handle's stream (tmh_lattice_set_stream) and return without waiting.
+ * tmh_cg_solve, tmh_scalar_prod_r and tmh_norm2 wait for their result.
+ *
+ * Errors.  Every entry point returns a status; nothing aborts or throws.
+ * Kernel faults are asynchronous and surface as TMH_ERR_HIP at the next
+ * call that waits.
+ */
+#ifndef TMHOP_H
+#define TMHOP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TMH_OK = 0,
+    TMH_ERR_ARG = -1,           /* null pointer, bad enum, bad size          */
+    TMH_ERR_GEOMETRY = -2,      /* an extent odd or < 2, or volume too large  */
+    TMH_ERR_ALIAS = -3,         /* output buffer overlaps an input buffer     */
+    TMH_ERR_HIP = -4,           /* a HIP runtime call failed                  */
+    TMH_ERR_NOMEM = -5,         /* device allocation of scratch failed        */
+    TMH_ERR_NOT_CONVERGED = -6, /* CG hit max_iter; x holds the last iterate  */
+    TMH_ERR_UNSUPPORTED = -7    /* precision or feature not built             */
+} tmh_status;
+
+typedef enum { TMH_EO = 0 /* odd -> even */, TMH_OE = 1 /* even -> odd */ } tmh_dir;
+
+typedef enum { TMH_F64 = 0, TMH_F32 = 1 } tmh_prec;
+
+typedef struct tmh_lattice tmh_lattice;
+
+/* Creates a lattice handle for dims = {T, LX, LY, LZ} on HIP device `device`,
+ * enqueueing on `hip_stream` (a hipStream_t, NULL = the null stream).
+ * TMH_ERR_GEOMETRY if an extent is odd or < 2, or V = T*LX*LY*LZ > 2^30.
+ * TMH_ERR_HIP if the device does not exist. */
+tmh_status tmh_lattice_create(tmh_lattice** out, const int dims[4], int device, void* hip_stream);
+void tmh_lattice_destroy(tmh_lattice* lat);
+tmh_status tmh_lattice_set_stream(tmh_lattice* lat, void* hip_stream);
+
+/* Even-odd half volume Vh and the padded site stride S. */
+size_t tmh_half_volume(const tmh_lattice* lat);
+size_t tmh_site_stride(const tmh_lattice* lat);
+/* Bytes of one internal spinor (one parity) / gauge field (both parities);
+ * 0 for an unknown precision. */
+size_t tmh_spinor_bytes(const tmh_lattice* lat, tmh_prec prec);
+size_t tmh_gauge_bytes(const tmh_lattice* lat, tmh_prec prec);
+
+/* Canonical FP64 -> internal layout in precision `prec` (rounded to nearest
+ * for TMH_F32), and back.  src and dst are device buffers and must not
+ * overlap (TMH_ERR_ALIAS). */
+tmh_status tmh_gauge_import(tmh_lattice* lat, void* dst, const double* src, tmh_prec prec);
+tmh_status tmh_spinor_import(tmh_lattice* lat, void* dst, const double* src, tmh_prec prec);
+tmh_status tmh_spinor_export(tmh_lattice* lat, double* dst, const void* src, tmh_prec prec);
+
+/* Hopping matrix (Section 2): out = H_eo in (TMH_EO: in odd, out even) or
+ * out = H_oe in (TMH_OE: in even, out odd); kappa is folded in, theta[4] are
+ * the boundary phases in units of pi.  gauge, in and out are internal-layout
+ * buffers of precision `prec`; out must not overlap in or gauge. */
+tmh_status tmh_hop_apply(tmh_lattice* lat, tmh_dir dir, void* out, const void* gauge,
+                         const void* in, double kappa, const double theta[4], tmh_prec prec);
+
+/* Even-odd twisted-mass operator (introduction): out = Qhat(sign) in on odd
+ * fields, sign = +1 or -1, with mt = 2*kappa*mu.  Two fused hopping-matrix
+ * launches: the first stores A^-1 H_eo in into the handle's even scratch, the
+ * second forms gamma_5 [A in - H_oe (.)].  out must not overlap in or gauge. */
+tmh_status tmh_qtm_apply(tmh_lattice* lat, void* out, const void* gauge, const void* in,
+                         double kappa, double mu, const double theta[4], int sign,
+                         tmh_prec prec);
+
+/* CG (the paper's inverter, Section 3) on Qhat(+)^dagger Qhat(+) x = b.
+ * x (FP64 internal layout, odd) holds the initial guess on entry and the
+ * solution on return; b is FP64.  Stops when |r|^2 <= rel_tol^2 |b|^2 on the
+ * recursive residual, then recomputes the true residual in FP64 and restarts
+ * from x if it is above rel_tol (at most 3 restarts).
+ *   inner = TMH_F64: plain FP64 CG.
+ *   inner = TMH_F32: defect correction -- the FP64 outer loop forms the true
+ *           residual, updates x and does every global reduction in FP64 on
+ *           the device; each inner solve runs CG with the FP32 hopping matrix
+ *           on an FP32 copy of the links made inside this call.
+ * *iters receives the number of operator (Qhat^dagger Qhat) applications in
+ * CG recursions (inner ones for mixed precision), *true_rel_res the final
+ * |b - A x| / |b|.  TMH_ERR_NOT_CONVERGED if max_iter is reached.  Blocks. */
+tmh_status tmh_cg_solve(tmh_lattice* lat, void* x, const void* b, const void* gauge,
+                        double kappa, double mu, const double theta[4], double rel_tol,
+                        int max_iter, tmh_prec inner, int* iters, double* true_rel_res);
+
+/* Gauge-link derivative ("fermionic derivative", Section 2, race conditions):
+ * not built in this library yet; returns TMH_ERR_UNSUPPORTED. */
+tmh_status tmh_hop_force(tmh_lattice* lat, tmh_dir dir, double* force, const void* gauge,
+                         const void* left, const void* right, double kappa,
+                         const double theta[4], double coeff);
+
+/* scalar_prod_r (Section 3): *result = Re <a, b> = Re sum conj(a) b over one
+ * parity, in FP64 with a deterministic two-pass reduction.  Blocks. */
+tmh_status tmh_scalar_prod_r(tmh_lattice* lat, double* result, const void* a, const void* b,
+                             tmh_prec prec);
+/* *result = |a|^2, same reduction.  Blocks. */
+tmh_status tmh_norm2(tmh_lattice* lat, double* result, const void* a, tmh_prec prec);
+
+/* Launch timing.  Section 3 of the paper measures where the hopping matrix
+ * and the solver spend their time; this is the device-side equivalent.  With
+ * timing enabled, every hopping-matrix launch made through the handle (by
+ * tmh_hop_apply, tmh_qtm_apply and tmh_cg_solve) is bracketed by two HIP
+ * events on the handle's stream.  tmh_profile_enable(on) resets the totals.
+ * tmh_profile_read waits for the recorded launches and returns, for one
+ * kernel kind, the number of launches and their summed duration in ms since
+ * the last reset.  Kinds: 3*prec + mode, where prec is TMH_F64 (0) or TMH_F32
+ * (1) and mode is 0 (plain hop, or hop with the A^-1 store), 1 (hop with the
+ * gamma_5 [A in - .] epilogue), 2 (as 1, plus the fused norm). */
+#define TMH_PROFILE_KINDS 6
+tmh_status tmh_profile_enable(tmh_lattice* lat, int on);
+tmh_status tmh_profile_read(tmh_lattice* lat, int kind, long long* launches, double* total_ms);
+
+const char* tmh_status_string(tmh_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TMHOP_H */

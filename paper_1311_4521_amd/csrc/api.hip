@@ -1,0 +1,588 @@
+// C-ABI of libtmhop (declared in include/tmhop.h): lattice handle, argument
+// checks, the hopping-matrix and twisted-mass launchers, the CG drivers.
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/tmhop.h"
+#include "common.h"
+#include "kernels.h"
+
+using tmh::Geo;
+using tmh::HopArgs;
+
+struct tmh_lattice {
+    int dims[4];
+    int device;
+    hipStream_t stream;
+    Geo g;
+    int npartial;           // partial-sum slots (max of hop and BLAS grids)
+    double* partial;        // reduction partials
+    double* scal;           // CG scalars (tmh::CgScal)
+    int* flags;             // {done, iterations}
+    double* h_scal;         // pinned host mirror of scal
+    int* h_flags;           // pinned host mirror of flags
+    void* even[2];          // intermediate even field per precision (Qtm)
+    double2* v64[4];        // FP64 CG vectors r, p, v, q
+    float2* v32[5];         // FP32 inner CG vectors r, p, v, q, d
+    float2* gauge32;        // FP32 copy of the links for the mixed-precision inner solve
+    // launch timing (tmh_profile_*): event pairs around hopping-matrix launches
+    struct EventPair {
+        hipEvent_t start, stop;
+        int kind;
+    };
+    bool prof_on;
+    std::vector<EventPair> prof_pending;
+    std::vector<EventPair> prof_free;
+    double prof_ms[TMH_PROFILE_KINDS];
+    long long prof_count[TMH_PROFILE_KINDS];
+};
+
+namespace {
+
+struct DeviceGuard {
+    int old = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&old) != hipSuccess) old = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (old >= 0) (void)hipSetDevice(old);
+    }
+};
+
+#define TMH_TRY_HIP(expr)                            \
+    do {                                             \
+        if ((expr) != hipSuccess) return TMH_ERR_HIP; \
+    } while (0)
+
+#define TMH_TRY(expr)                   \
+    do {                                \
+        tmh_status st__ = (expr);       \
+        if (st__ != TMH_OK) return st__; \
+    } while (0)
+
+size_t word_bytes(tmh_prec p) { return p == TMH_F64 ? 16 : (p == TMH_F32 ? 8 : 0); }
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+tmh_status ensure(void** p, size_t bytes) {
+    if (*p) return TMH_OK;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return TMH_ERR_NOMEM;
+    }
+    return TMH_OK;
+}
+
+size_t spinor_bytes(const tmh_lattice* l, tmh_prec p) { return (size_t)12 * l->g.S * word_bytes(p); }
+size_t gauge_bytes(const tmh_lattice* l, tmh_prec p) { return (size_t)72 * l->g.S * word_bytes(p); }
+
+tmh_status even_scratch(tmh_lattice* l, tmh_prec p, void** out) {
+    TMH_TRY(ensure(&l->even[p], spinor_bytes(l, p)));
+    *out = l->even[p];
+    return TMH_OK;
+}
+
+template <typename R>
+HopArgs<R> hop_args(const tmh_lattice* l, int pout, void* out, const void* gauge, const void* in,
+                    const double theta[4]) {
+    using W = typename tmh::Word<R>::T;
+    HopArgs<R> a;
+    memset(&a, 0, sizeof a);
+    a.out = (W*)out;
+    a.in = (const W*)in;
+    const W* g = (const W*)gauge;
+    a.gout = g + (int64_t)pout * 36 * l->g.S;
+    a.gin = g + (int64_t)(1 - pout) * 36 * l->g.S;
+    a.g = l->g;
+    a.pout = pout;
+    for (int m = 0; m < 4; ++m) {
+        a.ph_re[m] = (R)cos(M_PI * theta[m]);
+        a.ph_im[m] = (R)sin(M_PI * theta[m]);
+    }
+    return a;
+}
+
+// Folds the durations of all recorded event pairs into the totals (waits).
+tmh_status prof_flush(tmh_lattice* l) {
+    for (auto& e : l->prof_pending) {
+        if (hipEventSynchronize(e.stop) != hipSuccess) return TMH_ERR_HIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e.start, e.stop) != hipSuccess) return TMH_ERR_HIP;
+        l->prof_ms[e.kind] += ms;
+        l->prof_count[e.kind] += 1;
+        l->prof_free.push_back(e);
+    }
+    l->prof_pending.clear();
+    return TMH_OK;
+}
+
+constexpr size_t kMaxPendingEvents = 1024;
+
+// Launches one hopping-matrix kernel; with timing on, brackets it with a pair
+// of events on the handle's stream.
+template <typename R>
+hipError_t hop_launch(tmh_lattice* l, const HopArgs<R>& a, int mode) {
+    if (!l->prof_on) return tmh::launch_hop<R>(a, mode, l->stream);
+    if (l->prof_pending.size() >= kMaxPendingEvents && prof_flush(l) != TMH_OK) return hipErrorUnknown;
+    tmh_lattice::EventPair e;
+    if (!l->prof_free.empty()) {
+        e = l->prof_free.back();
+        l->prof_free.pop_back();
+    } else {
+        if (hipEventCreate(&e.start) != hipSuccess) return hipErrorUnknown;
+        if (hipEventCreate(&e.stop) != hipSuccess) {
+            (void)hipEventDestroy(e.start);
+            return hipErrorUnknown;
+        }
+    }
+    e.kind = (sizeof(R) == 8 ? 0 : 3) + mode;
+    hipError_t err = hipEventRecord(e.start, l->stream);
+    if (err == hipSuccess) err = tmh::launch_hop<R>(a, mode, l->stream);
+    if (err == hipSuccess) err = hipEventRecord(e.stop, l->stream);
+    if (err != hipSuccess) {
+        l->prof_free.push_back(e);
+        return err;
+    }
+    l->prof_pending.push_back(e);
+    return hipSuccess;
+}
+
+// Qhat(sign) in -> out through the even scratch `te`; with `partial` the
+// second launch also writes the |out|^2 partials.
+template <typename R>
+tmh_status qtm_launch(tmh_lattice* l, void* out, const void* gauge, const void* in, void* te, double kappa,
+                      double mu, const double theta[4], int sign, double* partial, const int* done) {
+    const double mt = 2.0 * kappa * mu * sign;
+    const double D = 1.0 + mt * mt;
+    HopArgs<R> a = hop_args<R>(l, 0, te, gauge, in, theta);
+    a.done = done;
+    // A^-1 = (1 - i mt gamma_5)/D: upper spins (1 - i mt)/D, lower (1 + i mt)/D
+    a.c_re[0] = (R)(kappa / D);
+    a.c_im[0] = (R)(-kappa * mt / D);
+    a.c_re[1] = (R)(kappa / D);
+    a.c_im[1] = (R)(kappa * mt / D);
+    TMH_TRY_HIP(hop_launch<R>(l, a, 0));
+    HopArgs<R> b = hop_args<R>(l, 1, out, gauge, te, theta);
+    b.done = done;
+    b.aux = (const typename tmh::Word<R>::T*)in;
+    b.partial = partial;
+    // gamma_5 [A in - kappa H te]: upper (1 + i mt) in - kappa H te,
+    // lower kappa H te - (1 - i mt) in
+    b.c_re[0] = (R)(-kappa);
+    b.c_re[1] = (R)kappa;
+    b.d_re[0] = (R)1;
+    b.d_im[0] = (R)mt;
+    b.d_re[1] = (R)-1;
+    b.d_im[1] = (R)mt;
+    TMH_TRY_HIP(hop_launch<R>(l, b, partial ? 2 : 1));
+    return TMH_OK;
+}
+
+tmh_status check_lat(const tmh_lattice* l) { return l ? TMH_OK : TMH_ERR_ARG; }
+
+tmh_status check_prec(tmh_prec p) { return (p == TMH_F64 || p == TMH_F32) ? TMH_OK : TMH_ERR_UNSUPPORTED; }
+
+tmh_status check_theta(const double* theta) {
+    if (!theta) return TMH_ERR_ARG;
+    for (int m = 0; m < 4; ++m)
+        if (!isfinite(theta[m])) return TMH_ERR_ARG;
+    return TMH_OK;
+}
+
+// Host copy of n device doubles / ints from the scalar area (waits).
+tmh_status read_scalars(tmh_lattice* l) {
+    TMH_TRY_HIP(hipMemcpyAsync(l->h_scal, l->scal, sizeof(double) * tmh::kNScal, hipMemcpyDeviceToHost,
+                               l->stream));
+    TMH_TRY_HIP(hipMemcpyAsync(l->h_flags, l->flags, sizeof(int) * 2, hipMemcpyDeviceToHost, l->stream));
+    TMH_TRY_HIP(hipStreamSynchronize(l->stream));
+    return TMH_OK;
+}
+
+template <typename R>
+tmh_status reduce_dot(tmh_lattice* l, double* result, const void* a, const void* b) {
+    using W = typename tmh::Word<R>::T;
+    TMH_TRY_HIP(tmh::launch_dot_partial<R>(l->partial, (const W*)a, (const W*)b, l->g, nullptr, l->stream));
+    TMH_TRY_HIP(tmh::launch_reduce(l->scal + tmh::kNorm, l->partial, tmh::blas_blocks(l->g), nullptr,
+                                   l->stream));
+    TMH_TRY(read_scalars(l));
+    *result = l->h_scal[tmh::kNorm];
+    return TMH_OK;
+}
+
+// r = b - Qhat(-) Qhat(+) x in precision R, and |r|^2 (waits).
+template <typename R>
+tmh_status true_residual(tmh_lattice* l, void* r, const void* b, const void* x, void* v, void* q, void* te,
+                         const void* gauge, double kappa, double mu, const double theta[4], double* rr) {
+    using W = typename tmh::Word<R>::T;
+    TMH_TRY(qtm_launch<R>(l, v, gauge, x, te, kappa, mu, theta, +1, nullptr, nullptr));
+    TMH_TRY(qtm_launch<R>(l, q, gauge, v, te, kappa, mu, theta, -1, nullptr, nullptr));
+    TMH_TRY_HIP(tmh::launch_sub_norm<R>((W*)r, (const W*)b, (const W*)q, l->partial, l->g, l->stream));
+    TMH_TRY_HIP(tmh::launch_reduce(l->scal + tmh::kNorm, l->partial, tmh::blas_blocks(l->g), nullptr,
+                                   l->stream));
+    TMH_TRY(read_scalars(l));
+    *rr = l->h_scal[tmh::kNorm];
+    return TMH_OK;
+}
+
+// CG recursion on A x = r0 where x holds the start vector and r holds
+// r0 - A x.  Iterates until |r|^2 <= stop or max_iter; scalars stay on the
+// device, the host looks at the flags once every kChunk iterations.
+constexpr int kChunk = 8;
+
+template <typename R>
+tmh_status cg_recursion(tmh_lattice* l, void* x, void* r, void* p, void* v, void* q, void* te, const void* gauge,
+                        double kappa, double mu, const double theta[4], double stop, int max_iter, int* iters) {
+    using W = typename tmh::Word<R>::T;
+    const int nb_hop = tmh::hop_blocks(l->g), nb_blas = tmh::blas_blocks(l->g);
+    // rr = |r|^2 into scal, flags reset
+    TMH_TRY_HIP(tmh::launch_dot_partial<R>(l->partial, (const W*)r, (const W*)r, l->g, nullptr, l->stream));
+    TMH_TRY_HIP(tmh::launch_cg_init(l->scal, l->partial, nb_blas, l->flags, stop, l->stream));
+    TMH_TRY_HIP(tmh::launch_copy<R>((W*)p, (const W*)r, l->g, l->stream));
+    *iters = 0;
+    if (max_iter <= 0) return TMH_OK;
+    for (;;) {
+        for (int k = 0; k < kChunk; ++k) {
+            // v = Qhat(+) p with |v|^2 = (p, A p)
+            TMH_TRY(qtm_launch<R>(l, v, gauge, p, te, kappa, mu, theta, +1, l->partial, l->flags));
+            TMH_TRY_HIP(tmh::launch_cg_alpha<R>(l->scal, l->partial, nb_hop, l->flags, l->stream));
+            // q = Qhat(-) v = A p
+            TMH_TRY(qtm_launch<R>(l, q, gauge, v, te, kappa, mu, theta, -1, nullptr, l->flags));
+            TMH_TRY_HIP(tmh::launch_cg_xr<R>((W*)x, (W*)r, (const W*)p, (const W*)q, l->scal, l->partial, l->g,
+                                             l->flags, l->stream));
+            TMH_TRY_HIP(tmh::launch_cg_beta(l->scal, l->partial, nb_blas, l->flags, max_iter, l->stream));
+            TMH_TRY_HIP(tmh::launch_cg_p<R>((W*)p, (const W*)r, l->scal, l->g, l->flags, l->stream));
+        }
+        TMH_TRY(read_scalars(l));
+        if (l->h_flags[0]) break;
+    }
+    *iters = l->h_flags[1];
+    return TMH_OK;
+}
+
+tmh_status alloc_cg64(tmh_lattice* l) {
+    for (int k = 0; k < 4; ++k) TMH_TRY(ensure((void**)&l->v64[k], spinor_bytes(l, TMH_F64)));
+    void* te;
+    return even_scratch(l, TMH_F64, &te);
+}
+
+tmh_status alloc_cg32(tmh_lattice* l) {
+    for (int k = 0; k < 5; ++k) TMH_TRY(ensure((void**)&l->v32[k], spinor_bytes(l, TMH_F32)));
+    TMH_TRY(ensure((void**)&l->gauge32, gauge_bytes(l, TMH_F32)));
+    void* te;
+    return even_scratch(l, TMH_F32, &te);
+}
+
+tmh_status cg_fp64(tmh_lattice* l, void* x, const void* b, const void* gauge, double kappa, double mu,
+                   const double theta[4], double tol, int max_iter, int* iters, double* res) {
+    TMH_TRY(alloc_cg64(l));
+    void *r = l->v64[0], *p = l->v64[1], *v = l->v64[2], *q = l->v64[3], *te = l->even[TMH_F64];
+    double bb;
+    TMH_TRY(reduce_dot<double>(l, &bb, b, b));
+    *iters = 0;
+    *res = 0.0;
+    if (bb == 0.0) {
+        TMH_TRY_HIP(tmh::launch_zero<double>((double2*)x, l->g, l->stream));
+        TMH_TRY_HIP(hipStreamSynchronize(l->stream));
+        return TMH_OK;
+    }
+    const double stop = tol * tol * bb;
+    double rr;
+    TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
+    int total = 0;
+    for (int restart = 0;; ++restart) {
+        *res = sqrt(rr / bb);
+        if (*res <= tol) return *iters = total, TMH_OK;
+        if (restart > 3 || total >= max_iter) break;
+        int it = 0;
+        TMH_TRY(cg_recursion<double>(l, x, r, p, v, q, te, gauge, kappa, mu, theta, stop, max_iter - total, &it));
+        total += it;
+        TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
+    }
+    *iters = total;
+    return TMH_ERR_NOT_CONVERGED;
+}
+
+// Defect correction: FP64 true residual and solution update, FP32 inner CG.
+constexpr double kInnerTolMin = 1e-5;
+constexpr int kMaxOuter = 64;
+
+tmh_status cg_mixed(tmh_lattice* l, void* x, const void* b, const void* gauge, double kappa, double mu,
+                    const double theta[4], double tol, int max_iter, int* iters, double* res) {
+    TMH_TRY(alloc_cg64(l));
+    TMH_TRY(alloc_cg32(l));
+    void *r = l->v64[0], *v = l->v64[2], *q = l->v64[3], *te = l->even[TMH_F64];
+    float2 *r32 = l->v32[0], *p32 = l->v32[1], *v32 = l->v32[2], *q32 = l->v32[3], *d32 = l->v32[4];
+    void* te32 = l->even[TMH_F32];
+    TMH_TRY_HIP(tmh::launch_narrow(l->gauge32, (const double2*)gauge, 72, l->g, l->stream));
+    double bb;
+    TMH_TRY(reduce_dot<double>(l, &bb, b, b));
+    *iters = 0;
+    *res = 0.0;
+    if (bb == 0.0) {
+        TMH_TRY_HIP(tmh::launch_zero<double>((double2*)x, l->g, l->stream));
+        TMH_TRY_HIP(hipStreamSynchronize(l->stream));
+        return TMH_OK;
+    }
+    double rr;
+    TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
+    int total = 0;
+    for (int outer = 0;; ++outer) {
+        *res = sqrt(rr / bb);
+        if (*res <= tol) return *iters = total, TMH_OK;
+        if (outer >= kMaxOuter || total >= max_iter) break;
+        // inner target: the remaining factor, but no tighter than FP32 can hold
+        double inner = 0.5 * tol / *res;
+        if (inner < kInnerTolMin) inner = kInnerTolMin;
+        TMH_TRY_HIP(tmh::launch_narrow(r32, (const double2*)r, 12, l->g, l->stream));
+        TMH_TRY_HIP(tmh::launch_zero<float>(d32, l->g, l->stream));
+        int it = 0;
+        // |r32|^2 ~ rr; the stop test is relative to the narrowed residual
+        TMH_TRY(cg_recursion<float>(l, d32, r32, p32, v32, q32, te32, l->gauge32, kappa, mu, theta,
+                                    inner * inner * rr, max_iter - total, &it));
+        total += it;
+        TMH_TRY_HIP(tmh::launch_add_widen((double2*)x, d32, l->g, l->stream));
+        TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
+    }
+    *iters = total;
+    return TMH_ERR_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" {
+
+tmh_status tmh_lattice_create(tmh_lattice** out, const int dims[4], int device, void* hip_stream) {
+    if (!out || !dims) return TMH_ERR_ARG;
+    *out = nullptr;
+    int64_t V = 1;
+    for (int m = 0; m < 4; ++m) {
+        if (dims[m] < 2 || (dims[m] & 1)) return TMH_ERR_GEOMETRY;
+        V *= dims[m];
+        if (V > ((int64_t)1 << 30)) return TMH_ERR_GEOMETRY;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TMH_ERR_HIP;
+    DeviceGuard guard(device);
+    if (!guard.ok) return TMH_ERR_HIP;
+    tmh_lattice* l = new (std::nothrow) tmh_lattice();
+    if (!l) return TMH_ERR_NOMEM;
+    memcpy(l->dims, dims, sizeof l->dims);
+    l->device = device;
+    l->stream = (hipStream_t)hip_stream;
+    for (int m = 0; m < 4; ++m) l->g.L[m] = dims[m];
+    l->g.Vh = (int)(V / 2);
+    l->g.S = (int)((V / 2 + 63) / 64 * 64);
+    const int nh = tmh::hop_blocks(l->g), nbl = tmh::blas_blocks(l->g);
+    l->npartial = nh > nbl ? nh : nbl;
+    tmh_status st = ensure((void**)&l->partial, sizeof(double) * l->npartial);
+    if (st == TMH_OK) st = ensure((void**)&l->scal, sizeof(double) * tmh::kNScal);
+    if (st == TMH_OK) st = ensure((void**)&l->flags, sizeof(int) * 2);
+    if (st == TMH_OK && hipHostMalloc((void**)&l->h_scal, sizeof(double) * tmh::kNScal, hipHostMallocDefault) !=
+                            hipSuccess)
+        st = TMH_ERR_NOMEM;
+    if (st == TMH_OK &&
+        hipHostMalloc((void**)&l->h_flags, sizeof(int) * 2, hipHostMallocDefault) != hipSuccess)
+        st = TMH_ERR_NOMEM;
+    if (st != TMH_OK) {
+        tmh_lattice_destroy(l);
+        return st;
+    }
+    *out = l;
+    return TMH_OK;
+}
+
+void tmh_lattice_destroy(tmh_lattice* l) {
+    if (!l) return;
+    DeviceGuard guard(l->device);
+    (void)hipStreamSynchronize(l->stream);
+    (void)hipFree(l->partial);
+    (void)hipFree(l->scal);
+    (void)hipFree(l->flags);
+    if (l->h_scal) (void)hipHostFree(l->h_scal);
+    if (l->h_flags) (void)hipHostFree(l->h_flags);
+    for (void* p : l->even) (void)hipFree(p);
+    for (void* p : l->v64) (void)hipFree(p);
+    for (void* p : l->v32) (void)hipFree(p);
+    (void)hipFree(l->gauge32);
+    (void)prof_flush(l);
+    for (auto& e : l->prof_free) {
+        (void)hipEventDestroy(e.start);
+        (void)hipEventDestroy(e.stop);
+    }
+    delete l;
+}
+
+tmh_status tmh_lattice_set_stream(tmh_lattice* l, void* hip_stream) {
+    TMH_TRY(check_lat(l));
+    l->stream = (hipStream_t)hip_stream;
+    return TMH_OK;
+}
+
+size_t tmh_half_volume(const tmh_lattice* l) { return l ? (size_t)l->g.Vh : 0; }
+size_t tmh_site_stride(const tmh_lattice* l) { return l ? (size_t)l->g.S : 0; }
+size_t tmh_spinor_bytes(const tmh_lattice* l, tmh_prec p) { return l ? spinor_bytes(l, p) : 0; }
+size_t tmh_gauge_bytes(const tmh_lattice* l, tmh_prec p) { return l ? gauge_bytes(l, p) : 0; }
+
+tmh_status tmh_gauge_import(tmh_lattice* l, void* dst, const double* src, tmh_prec prec) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(prec));
+    if (!dst || !src) return TMH_ERR_ARG;
+    if (overlap(dst, gauge_bytes(l, prec), src, (size_t)2 * l->g.Vh * 4 * 9 * 16)) return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    if (prec == TMH_F64)
+        TMH_TRY_HIP(tmh::launch_gauge_import<double>((double2*)dst, src, l->g, l->stream));
+    else
+        TMH_TRY_HIP(tmh::launch_gauge_import<float>((float2*)dst, src, l->g, l->stream));
+    return TMH_OK;
+}
+
+tmh_status tmh_spinor_import(tmh_lattice* l, void* dst, const double* src, tmh_prec prec) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(prec));
+    if (!dst || !src) return TMH_ERR_ARG;
+    if (overlap(dst, spinor_bytes(l, prec), src, (size_t)l->g.Vh * 12 * 16)) return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    if (prec == TMH_F64)
+        TMH_TRY_HIP(tmh::launch_spinor_import<double>((double2*)dst, src, l->g, l->stream));
+    else
+        TMH_TRY_HIP(tmh::launch_spinor_import<float>((float2*)dst, src, l->g, l->stream));
+    return TMH_OK;
+}
+
+tmh_status tmh_spinor_export(tmh_lattice* l, double* dst, const void* src, tmh_prec prec) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(prec));
+    if (!dst || !src) return TMH_ERR_ARG;
+    if (overlap(dst, (size_t)l->g.Vh * 12 * 16, src, spinor_bytes(l, prec))) return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    if (prec == TMH_F64)
+        TMH_TRY_HIP(tmh::launch_spinor_export<double>(dst, (const double2*)src, l->g, l->stream));
+    else
+        TMH_TRY_HIP(tmh::launch_spinor_export<float>(dst, (const float2*)src, l->g, l->stream));
+    return TMH_OK;
+}
+
+tmh_status tmh_hop_apply(tmh_lattice* l, tmh_dir dir, void* out, const void* gauge, const void* in, double kappa,
+                         const double theta[4], tmh_prec prec) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(prec));
+    TMH_TRY(check_theta(theta));
+    if (dir != TMH_EO && dir != TMH_OE) return TMH_ERR_ARG;
+    if (!out || !gauge || !in || !isfinite(kappa)) return TMH_ERR_ARG;
+    const size_t sb = spinor_bytes(l, prec);
+    if (overlap(out, sb, in, sb) || overlap(out, sb, gauge, gauge_bytes(l, prec))) return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    const int pout = dir == TMH_EO ? 0 : 1;
+    if (prec == TMH_F64) {
+        HopArgs<double> a = hop_args<double>(l, pout, out, gauge, in, theta);
+        a.c_re[0] = a.c_re[1] = kappa;
+        TMH_TRY_HIP(hop_launch<double>(l, a, 0));
+    } else {
+        HopArgs<float> a = hop_args<float>(l, pout, out, gauge, in, theta);
+        a.c_re[0] = a.c_re[1] = (float)kappa;
+        TMH_TRY_HIP(hop_launch<float>(l, a, 0));
+    }
+    return TMH_OK;
+}
+
+tmh_status tmh_qtm_apply(tmh_lattice* l, void* out, const void* gauge, const void* in, double kappa, double mu,
+                         const double theta[4], int sign, tmh_prec prec) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(prec));
+    TMH_TRY(check_theta(theta));
+    if (sign != 1 && sign != -1) return TMH_ERR_ARG;
+    if (!out || !gauge || !in || !isfinite(kappa) || !isfinite(mu)) return TMH_ERR_ARG;
+    const size_t sb = spinor_bytes(l, prec);
+    if (overlap(out, sb, in, sb) || overlap(out, sb, gauge, gauge_bytes(l, prec))) return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    void* te;
+    TMH_TRY(even_scratch(l, prec, &te));
+    if (prec == TMH_F64) return qtm_launch<double>(l, out, gauge, in, te, kappa, mu, theta, sign, nullptr, nullptr);
+    return qtm_launch<float>(l, out, gauge, in, te, kappa, mu, theta, sign, nullptr, nullptr);
+}
+
+tmh_status tmh_cg_solve(tmh_lattice* l, void* x, const void* b, const void* gauge, double kappa, double mu,
+                        const double theta[4], double rel_tol, int max_iter, tmh_prec inner, int* iters,
+                        double* true_rel_res) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(inner));
+    TMH_TRY(check_theta(theta));
+    if (!x || !b || !gauge || !iters || !true_rel_res) return TMH_ERR_ARG;
+    if (!isfinite(kappa) || !isfinite(mu) || !(rel_tol > 0.0) || max_iter < 0) return TMH_ERR_ARG;
+    const size_t sb = spinor_bytes(l, TMH_F64);
+    if (overlap(x, sb, b, sb) || overlap(x, sb, gauge, gauge_bytes(l, TMH_F64))) return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    tmh_status st = inner == TMH_F64 ? cg_fp64(l, x, b, gauge, kappa, mu, theta, rel_tol, max_iter, iters,
+                                               true_rel_res)
+                                     : cg_mixed(l, x, b, gauge, kappa, mu, theta, rel_tol, max_iter, iters,
+                                                true_rel_res);
+    if (hipStreamSynchronize(l->stream) != hipSuccess) return TMH_ERR_HIP;
+    return st;
+}
+
+tmh_status tmh_hop_force(tmh_lattice* l, tmh_dir, double*, const void*, const void*, const void*, double,
+                         const double*, double) {
+    TMH_TRY(check_lat(l));
+    return TMH_ERR_UNSUPPORTED;
+}
+
+tmh_status tmh_scalar_prod_r(tmh_lattice* l, double* result, const void* a, const void* b, tmh_prec prec) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(prec));
+    if (!result || !a || !b) return TMH_ERR_ARG;
+    DeviceGuard guard(l->device);
+    return prec == TMH_F64 ? reduce_dot<double>(l, result, a, b) : reduce_dot<float>(l, result, a, b);
+}
+
+tmh_status tmh_norm2(tmh_lattice* l, double* result, const void* a, tmh_prec prec) {
+    return tmh_scalar_prod_r(l, result, a, a, prec);
+}
+
+tmh_status tmh_profile_enable(tmh_lattice* l, int on) {
+    TMH_TRY(check_lat(l));
+    DeviceGuard guard(l->device);
+    TMH_TRY(prof_flush(l));
+    l->prof_on = on != 0;
+    for (int k = 0; k < TMH_PROFILE_KINDS; ++k) {
+        l->prof_ms[k] = 0.0;
+        l->prof_count[k] = 0;
+    }
+    return TMH_OK;
+}
+
+tmh_status tmh_profile_read(tmh_lattice* l, int kind, long long* launches, double* total_ms) {
+    TMH_TRY(check_lat(l));
+    if (kind < 0 || kind >= TMH_PROFILE_KINDS || !launches || !total_ms) return TMH_ERR_ARG;
+    DeviceGuard guard(l->device);
+    TMH_TRY(prof_flush(l));
+    *launches = l->prof_count[kind];
+    *total_ms = l->prof_ms[kind];
+    return TMH_OK;
+}
+
+const char* tmh_status_string(tmh_status st) {
+    switch (st) {
+        case TMH_OK: return "ok";
+        case TMH_ERR_ARG: return "invalid argument";
+        case TMH_ERR_GEOMETRY: return "invalid lattice geometry (extents must be even and >= 2)";
+        case TMH_ERR_ALIAS: return "output buffer overlaps an input buffer";
+        case TMH_ERR_HIP: return "HIP runtime error";
+        case TMH_ERR_NOMEM: return "device allocation failed";
+        case TMH_ERR_NOT_CONVERGED: return "CG did not converge within max_iter";
+        case TMH_ERR_UNSUPPORTED: return "unsupported precision or feature";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal device helpers of libtmhop: complex words, lattice geometry,
+// deterministic block reductions and the XCD-aware block mapping.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tmh {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
+constexpr int kXcds = 8;     // MI355X: 8 XCDs, workgroups dealt round-robin
+
+// Storage word of one complex number.
+template <typename R> struct Word;
+template <> struct Word<double> { using T = double2; };
+template <> struct Word<float> { using T = float2; };
+
+template <typename R> struct cx {
+    R re, im;
+};
+
+template <typename R> __device__ __forceinline__ cx<R> mk(R re, R im) { return {re, im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) {
+    return {a.re + b.re, a.im + b.im};
+}
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) {
+    return {a.re - b.re, a.im - b.im};
+}
+template <typename R> __device__ __forceinline__ cx<R> operator*(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) {
+    return {s * a.re, s * a.im};
+}
+// i * a
+template <typename R> __device__ __forceinline__ cx<R> mul_i(cx<R> a) { return {-a.im, a.re}; }
+// conj(a) * b
+template <typename R> __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ void operator+=(cx<R>& a, cx<R> b) {
+    a.re += b.re;
+    a.im += b.im;
+}
+template <typename R> __device__ __forceinline__ void operator-=(cx<R>& a, cx<R> b) {
+    a.re -= b.re;
+    a.im -= b.im;
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> ld(const typename Word<R>::T* __restrict__ p, int64_t k) {
+    typename Word<R>::T w = p[k];
+    return {w.x, w.y};
+}
+template <typename R>
+__device__ __forceinline__ void st(typename Word<R>::T* __restrict__ p, int64_t k, cx<R> v) {
+    typename Word<R>::T w;
+    w.x = v.re;
+    w.y = v.im;
+    p[k] = w;
+}
+
+// Lattice extents and strides as seen by the kernels.
+struct Geo {
+    int L[4];   // T, LX, LY, LZ
+    int Vh;     // sites per parity
+    int S;      // site stride of the structure-of-arrays layout (>= Vh)
+};
+
+// Coordinates and lex index of the site with even-odd index i on parity p:
+// lex = 2i + ((t + x + y + p) & 1) because LZ is even.
+__device__ __forceinline__ void site_coords(const Geo& g, int i, int p, int c[4], int& lex) {
+    const unsigned l2 = 2u * (unsigned)i;
+    const unsigned row = l2 / (unsigned)g.L[3];
+    const unsigned y = row % (unsigned)g.L[2];
+    const unsigned r2 = row / (unsigned)g.L[2];
+    const unsigned x = r2 % (unsigned)g.L[1];
+    const unsigned t = r2 / (unsigned)g.L[1];
+    const unsigned odd = (t + x + y + (unsigned)p) & 1u;
+    c[0] = (int)t;
+    c[1] = (int)x;
+    c[2] = (int)y;
+    c[3] = (int)(l2 - row * (unsigned)g.L[3] + odd);
+    lex = (int)(l2 + odd);
+}
+
+// Deal workgroups so that XCD k (which receives hardware blocks k, k+8, ...)
+// owns one contiguous range of logical blocks: neighbouring sites then share
+// that XCD's L2.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb / kXcds, r = nb % kXcds;
+    const int x = b % kXcds, k = b / kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Sum over a workgroup of kBlock threads, in a fixed order; the result is
+// valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __shared__ double wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) wsum[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += wsum[w];
+    }
+    return s;
+}
+
+}  // namespace tmh

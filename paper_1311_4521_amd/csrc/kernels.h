@@ -1,0 +1,77 @@
+// Host-side launch interface of the device kernels (internal to libtmhop).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace tmh {
+
+template <typename R> struct HopArgs {
+    typename Word<R>::T* out;
+    const typename Word<R>::T* in;
+    const typename Word<R>::T* gout;  // links U_mu(x) of the output parity
+    const typename Word<R>::T* gin;   // links U_mu(y) of the input parity
+    const typename Word<R>::T* aux;   // MODE >= 1: field added at the output site
+    double* partial;                  // MODE 2: per-workgroup |out|^2
+    const int* done;                  // optional device flag: skip when set
+    Geo g;
+    int pout;                         // parity of the output sites
+    R ph_re[4], ph_im[4];             // exp(i pi theta_mu)
+    R c_re[2], c_im[2];               // coefficient of the hopping sum, upper/lower spins
+    R d_re[2], d_im[2];               // coefficient of aux, upper/lower spins
+};
+
+int hop_blocks(const Geo& g);
+template <typename R> hipError_t launch_hop(const HopArgs<R>& a, int mode, hipStream_t s);
+
+// Layout conversion (layout.hip).
+template <typename R>
+hipError_t launch_gauge_import(typename Word<R>::T* dst, const double* src, const Geo& g, hipStream_t s);
+template <typename R>
+hipError_t launch_spinor_import(typename Word<R>::T* dst, const double* src, const Geo& g, hipStream_t s);
+template <typename R>
+hipError_t launch_spinor_export(double* dst, const typename Word<R>::T* src, const Geo& g, hipStream_t s);
+// Internal FP64 -> FP32 (spinor: ncomp = 12, gauge: ncomp = 72), and FP32 -> FP64.
+hipError_t launch_narrow(float2* dst, const double2* src, int ncomp, const Geo& g, hipStream_t s);
+hipError_t launch_widen(double2* dst, const float2* src, int ncomp, const Geo& g, hipStream_t s);
+
+// BLAS-1 and reductions (blas.hip).  All reductions write per-workgroup
+// partials; reduce_partials sums them in a fixed order into out[0].
+int blas_blocks(const Geo& g);
+template <typename R>
+hipError_t launch_dot_partial(double* partial, const typename Word<R>::T* a, const typename Word<R>::T* b,
+                              const Geo& g, const int* done, hipStream_t s);
+hipError_t launch_reduce(double* out, const double* partial, int n, const int* done, hipStream_t s);
+
+// CG building blocks on one parity.  scal[] holds the device scalars
+// (see CgScal), flags[] = {done, iterations}.
+enum CgScal { kRR = 0, kPQ = 1, kAlpha = 2, kBeta = 3, kStop = 4, kRRNew = 5, kNorm = 6, kNScal = 8 };
+template <typename R>
+hipError_t launch_cg_alpha(double* scal, const double* partial, int n, int* flags, hipStream_t s);
+template <typename R>
+hipError_t launch_cg_xr(typename Word<R>::T* x, typename Word<R>::T* r, const typename Word<R>::T* p,
+                        const typename Word<R>::T* q, const double* scal, double* partial, const Geo& g,
+                        const int* flags, hipStream_t s);
+hipError_t launch_cg_beta(double* scal, const double* partial, int n, int* flags, int max_iter,
+                          hipStream_t s);
+template <typename R>
+hipError_t launch_cg_p(typename Word<R>::T* p, const typename Word<R>::T* r, const double* scal,
+                       const Geo& g, const int* flags, hipStream_t s);
+// out = a - b, with |out|^2 partials (true residual).
+template <typename R>
+hipError_t launch_sub_norm(typename Word<R>::T* out, const typename Word<R>::T* a,
+                           const typename Word<R>::T* b, double* partial, const Geo& g, hipStream_t s);
+// x += y (FP64 x, FP32 y): defect-correction update.
+hipError_t launch_add_widen(double2* x, const float2* y, const Geo& g, hipStream_t s);
+template <typename R>
+hipError_t launch_copy(typename Word<R>::T* dst, const typename Word<R>::T* src, const Geo& g, hipStream_t s);
+template <typename R>
+hipError_t launch_zero(typename Word<R>::T* dst, const Geo& g, hipStream_t s);
+// Copies src to dst and resets the CG scalars: scal[kRR] = |src|^2 from the
+// given partials, flags = {0, 0}.
+hipError_t launch_cg_init(double* scal, const double* partial, int n, int* flags, double stop,
+                          hipStream_t s);
+
+}  // namespace tmh

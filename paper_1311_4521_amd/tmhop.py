@@ -1,0 +1,336 @@
+"""Thin ctypes binding of libtmhop.so (the C-ABI of ``include/tmhop.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  torch supplies device memory (field buffers are
+torch tensors; their ``data_ptr()`` is passed) and the stream (the current
+torch stream is installed on the handle before every call).  If the library
+has not been built this module raises at import: there is no fallback.
+
+Internal field tensors (see ``include/tmhop.h`` for the layout):
+
+* spinor, one parity: ``float64``/``float32`` tensor of shape ``(12, S, 2)``
+  -- component ``3*spin + colour``, site, (re, im);
+* gauge field: shape ``(2, 4, 9, S, 2)`` -- parity, mu, ``3*row + col``,
+  site, (re, im).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("TMHOP_LIB", os.path.join(_HERE, "libtmhop.so"))
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first "
+        "(python -c 'import __graft_entry__ as g; g.build()')")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+TMH_OK = 0
+TMH_ERR_ARG = -1
+TMH_ERR_GEOMETRY = -2
+TMH_ERR_ALIAS = -3
+TMH_ERR_HIP = -4
+TMH_ERR_NOMEM = -5
+TMH_ERR_NOT_CONVERGED = -6
+TMH_ERR_UNSUPPORTED = -7
+
+EO, OE = 0, 1
+F64, F32 = 0, 1
+_DIRS = {"eo": EO, "oe": OE, EO: EO, OE: OE}
+_PRECS = {"f64": F64, "f32": F32, F64: F64, F32: F32}
+_DTYPE = {F64: torch.float64, F32: torch.float32}
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_S = ctypes.c_size_t
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("tmh_lattice_create", _I, [ctypes.POINTER(_P), _P, _I, _P])
+_sig("tmh_lattice_destroy", None, [_P])
+_sig("tmh_lattice_set_stream", _I, [_P, _P])
+_sig("tmh_half_volume", _S, [_P])
+_sig("tmh_site_stride", _S, [_P])
+_sig("tmh_spinor_bytes", _S, [_P, _I])
+_sig("tmh_gauge_bytes", _S, [_P, _I])
+_sig("tmh_gauge_import", _I, [_P, _P, _P, _I])
+_sig("tmh_spinor_import", _I, [_P, _P, _P, _I])
+_sig("tmh_spinor_export", _I, [_P, _P, _P, _I])
+_sig("tmh_hop_apply", _I, [_P, _I, _P, _P, _P, _D, _P, _I])
+_sig("tmh_qtm_apply", _I, [_P, _P, _P, _P, _D, _D, _P, _I, _I])
+_sig("tmh_cg_solve", _I, [_P, _P, _P, _P, _D, _D, _P, _D, _I, _I, ctypes.POINTER(_I),
+                          ctypes.POINTER(_D)])
+_sig("tmh_hop_force", _I, [_P, _I, _P, _P, _P, _P, _D, _P, _D])
+_sig("tmh_scalar_prod_r", _I, [_P, ctypes.POINTER(_D), _P, _P, _I])
+_sig("tmh_norm2", _I, [_P, ctypes.POINTER(_D), _P, _I])
+_sig("tmh_profile_enable", _I, [_P, _I])
+_sig("tmh_profile_read", _I, [_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D)])
+_sig("tmh_status_string", ctypes.c_char_p, [_I])
+
+EXPORTED = ("tmh_lattice_create", "tmh_lattice_destroy", "tmh_lattice_set_stream",
+            "tmh_half_volume", "tmh_site_stride", "tmh_spinor_bytes", "tmh_gauge_bytes",
+            "tmh_gauge_import", "tmh_spinor_import", "tmh_spinor_export", "tmh_hop_apply",
+            "tmh_qtm_apply", "tmh_cg_solve", "tmh_hop_force", "tmh_scalar_prod_r", "tmh_norm2",
+            "tmh_profile_enable", "tmh_profile_read", "tmh_status_string")
+
+
+class TmhError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+def status_string(status: int) -> str:
+    return _lib.tmh_status_string(int(status)).decode()
+
+
+def _check(status: int, what: str):
+    if status != TMH_OK:
+        raise TmhError(status, what)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _theta(theta):
+    arr = (ctypes.c_double * 4)(*[float(x) for x in theta])
+    return ctypes.cast(arr, _P), arr
+
+
+def _stream_ptr(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Lattice:
+    """Lattice handle for dims = (T, LX, LY, LZ) on one HIP device."""
+
+    def __init__(self, dims, device=None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.dims = tuple(int(d) for d in dims)
+        self.device = torch.device("cuda", int(device))
+        h = _P()
+        d = (ctypes.c_int * 4)(*self.dims)
+        _check(_lib.tmh_lattice_create(ctypes.byref(h), ctypes.cast(d, _P), int(device),
+                                       _P(_stream_ptr(self.device))), "tmh_lattice_create")
+        self._h = h
+        self.Vh = int(_lib.tmh_half_volume(h))
+        self.S = int(_lib.tmh_site_stride(h))
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("lattice handle already destroyed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.tmh_lattice_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _lib.tmh_lattice_set_stream(self.handle, _P(_stream_ptr(self.device)))
+
+    # -- buffers -------------------------------------------------------------
+    def spinor_bytes(self, prec=F64) -> int:
+        return int(_lib.tmh_spinor_bytes(self.handle, _PRECS[prec]))
+
+    def gauge_bytes(self, prec=F64) -> int:
+        return int(_lib.tmh_gauge_bytes(self.handle, _PRECS[prec]))
+
+    def new_spinor(self, prec=F64, zero=True):
+        p = _PRECS[prec]
+        f = torch.zeros if zero else torch.empty
+        return f((12, self.S, 2), dtype=_DTYPE[p], device=self.device)
+
+    def new_gauge(self, prec=F64):
+        p = _PRECS[prec]
+        return torch.empty((2, 4, 9, self.S, 2), dtype=_DTYPE[p], device=self.device)
+
+
+def _complex_dev(x, shape, device):
+    if not torch.is_tensor(x):
+        x = torch.from_numpy(x)
+    x = x.to(device=device, dtype=torch.complex128).contiguous()
+    if tuple(x.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(x.shape)}")
+    return x
+
+
+def _expect(t, lat, prec, kind):
+    shape = (12, lat.S, 2) if kind == "spinor" else (2, 4, 9, lat.S, 2)
+    if not torch.is_tensor(t) or t.device != lat.device or t.dtype != _DTYPE[prec] \
+            or tuple(t.shape) != shape or not t.is_contiguous():
+        raise ValueError(f"{kind} buffer must be a contiguous {_DTYPE[prec]} tensor of shape "
+                         f"{shape} on {lat.device}")
+
+
+# -- entry points (same names as the C-ABI, without the tmh_ prefix) ---------
+
+def lattice_create(dims, device=None) -> Lattice:
+    return Lattice(dims, device)
+
+
+def gauge_import(lat: Lattice, U, prec=F64, out=None):
+    """Canonical ``complex128[4][V][3][3]`` (numpy or torch) -> internal."""
+    p = _PRECS[prec]
+    V = 2 * lat.Vh
+    src = _complex_dev(U, (4, V, 3, 3), lat.device)
+    out = lat.new_gauge(p) if out is None else out
+    _expect(out, lat, p, "gauge")
+    lat._sync_stream()
+    _check(_lib.tmh_gauge_import(lat.handle, out.data_ptr(), src.data_ptr(), p), "tmh_gauge_import")
+    torch.cuda.current_stream(lat.device).synchronize()
+    return out
+
+
+def spinor_import(lat: Lattice, psi, prec=F64, out=None):
+    """Canonical ``complex128[Vh][4][3]`` -> internal spinor."""
+    p = _PRECS[prec]
+    src = _complex_dev(psi, (lat.Vh, 4, 3), lat.device)
+    out = lat.new_spinor(p) if out is None else out
+    _expect(out, lat, p, "spinor")
+    lat._sync_stream()
+    _check(_lib.tmh_spinor_import(lat.handle, out.data_ptr(), src.data_ptr(), p), "tmh_spinor_import")
+    torch.cuda.current_stream(lat.device).synchronize()
+    return out
+
+
+def spinor_export(lat: Lattice, src, prec=F64):
+    """Internal spinor -> canonical ``complex128[Vh][4][3]`` torch tensor on the device."""
+    p = _PRECS[prec]
+    _expect(src, lat, p, "spinor")
+    out = torch.empty((lat.Vh, 4, 3), dtype=torch.complex128, device=lat.device)
+    lat._sync_stream()
+    _check(_lib.tmh_spinor_export(lat.handle, out.data_ptr(), src.data_ptr(), p), "tmh_spinor_export")
+    return out
+
+
+def hop_apply(lat: Lattice, direction, out, gauge, inp, kappa, theta, prec=F64):
+    """out = H_eo inp (direction 'eo') or H_oe inp ('oe'); asynchronous."""
+    p = _PRECS[prec]
+    _expect(out, lat, p, "spinor")
+    _expect(inp, lat, p, "spinor")
+    _expect(gauge, lat, p, "gauge")
+    th, _keep = _theta(theta)
+    lat._sync_stream()
+    _check(_lib.tmh_hop_apply(lat.handle, _DIRS[direction], out.data_ptr(), gauge.data_ptr(),
+                              inp.data_ptr(), float(kappa), th, p), "tmh_hop_apply")
+    return out
+
+
+def qtm_apply(lat: Lattice, out, gauge, inp, kappa, mu, theta, sign=+1, prec=F64):
+    """out = Qhat(sign) inp on odd fields; asynchronous."""
+    p = _PRECS[prec]
+    _expect(out, lat, p, "spinor")
+    _expect(inp, lat, p, "spinor")
+    _expect(gauge, lat, p, "gauge")
+    th, _keep = _theta(theta)
+    lat._sync_stream()
+    _check(_lib.tmh_qtm_apply(lat.handle, out.data_ptr(), gauge.data_ptr(), inp.data_ptr(),
+                              float(kappa), float(mu), th, int(sign), p), "tmh_qtm_apply")
+    return out
+
+
+def cg_solve(lat: Lattice, x, b, gauge, kappa, mu, theta, rel_tol=1e-10, max_iter=10000,
+             inner=F64):
+    """CG on Qhat(+)^dagger Qhat(+) x = b (FP64 fields; x holds the guess).
+    Returns (iterations, true relative residual, converged)."""
+    _expect(x, lat, F64, "spinor")
+    _expect(b, lat, F64, "spinor")
+    _expect(gauge, lat, F64, "gauge")
+    th, _keep = _theta(theta)
+    it = ctypes.c_int(0)
+    res = ctypes.c_double(0.0)
+    lat._sync_stream()
+    st = _lib.tmh_cg_solve(lat.handle, x.data_ptr(), b.data_ptr(), gauge.data_ptr(), float(kappa),
+                           float(mu), th, float(rel_tol), int(max_iter), _PRECS[inner],
+                           ctypes.byref(it), ctypes.byref(res))
+    if st not in (TMH_OK, TMH_ERR_NOT_CONVERGED):
+        raise TmhError(st, "tmh_cg_solve")
+    return it.value, res.value, st == TMH_OK
+
+
+def hop_force(lat: Lattice, direction, force, gauge, left, right, kappa, theta, coeff):
+    th, _keep = _theta(theta)
+    lat._sync_stream()
+    _check(_lib.tmh_hop_force(lat.handle, _DIRS[direction], _ptr(force), _ptr(gauge), _ptr(left),
+                              _ptr(right), float(kappa), th, float(coeff)), "tmh_hop_force")
+
+
+def scalar_prod_r(lat: Lattice, a, b, prec=F64) -> float:
+    """Re <a, b> over one parity (FP64 deterministic reduction); waits."""
+    p = _PRECS[prec]
+    _expect(a, lat, p, "spinor")
+    _expect(b, lat, p, "spinor")
+    r = ctypes.c_double(0.0)
+    lat._sync_stream()
+    _check(_lib.tmh_scalar_prod_r(lat.handle, ctypes.byref(r), a.data_ptr(), b.data_ptr(), p),
+           "tmh_scalar_prod_r")
+    return r.value
+
+
+def norm2(lat: Lattice, a, prec=F64) -> float:
+    p = _PRECS[prec]
+    _expect(a, lat, p, "spinor")
+    r = ctypes.c_double(0.0)
+    lat._sync_stream()
+    _check(_lib.tmh_norm2(lat.handle, ctypes.byref(r), a.data_ptr(), p), "tmh_norm2")
+    return r.value
+
+
+PROFILE_KINDS = 6
+
+
+def profile_kind(prec, mode):
+    """Kernel kind index: 3*prec + mode (mode 0 plain/A^-1 store, 1 twist
+    epilogue, 2 twist epilogue with fused norm)."""
+    return 3 * _PRECS[prec] + int(mode)
+
+
+def profile_enable(lat: Lattice, on=True):
+    """Start (or stop) event timing of hopping-matrix launches; resets totals."""
+    lat._sync_stream()
+    _check(_lib.tmh_profile_enable(lat.handle, 1 if on else 0), "tmh_profile_enable")
+
+
+def profile_read(lat: Lattice, kind):
+    """(launches, total ms) of one kernel kind since the last reset; waits."""
+    n = ctypes.c_longlong(0)
+    ms = ctypes.c_double(0.0)
+    _check(_lib.tmh_profile_read(lat.handle, int(kind), ctypes.byref(n), ctypes.byref(ms)),
+           "tmh_profile_read")
+    return int(n.value), float(ms.value)
+
+
+def raw_lattice_create(dims, device=0):
+    """Calls tmh_lattice_create with no torch involvement; returns (status,
+    handle).  Used to check argument validation."""
+    h = _P()
+    d = (ctypes.c_int * 4)(*[int(x) for x in dims])
+    st = _lib.tmh_lattice_create(ctypes.byref(h), ctypes.cast(d, _P), int(device), None)
+    return st, h
