@@ -89,7 +89,8 @@ typedef struct tmh_lattice tmh_lattice;
 
 /* Creates a lattice handle for dims = {T, LX, LY, LZ} on HIP device `device`,
  * enqueueing on `hip_stream` (a hipStream_t, NULL = the null stream).
- * TMH_ERR_GEOMETRY if an extent is odd or < 2, or V = T*LX*LY*LZ > 2^30.
+ * TMH_ERR_GEOMETRY if an extent is odd or < 2, or V = T*LX*LY*LZ >= 2^29 - 64
+ * (one FP64 component array, 16 S bytes, must stay below 4 GiB).
  * TMH_ERR_HIP if the device does not exist. */
 tmh_status tmh_lattice_create(tmh_lattice** out, const int dims[4], int device, void* hip_stream);
 void tmh_lattice_destroy(tmh_lattice* lat);
@@ -154,6 +155,14 @@ tmh_status tmh_scalar_prod_r(tmh_lattice* lat, double* result, const void* a, co
                              tmh_prec prec);
 /* *result = |a|^2, same reduction.  Blocks. */
 tmh_status tmh_norm2(tmh_lattice* lat, double* result, const void* a, tmh_prec prec);
+
+/* Bandwidth reference for the roofline: copies nbytes (a multiple of 16,
+ * both buffers 16-byte aligned, not overlapping) from src to dst on the
+ * handle's stream with a plain streaming kernel (non-temporal 16-byte loads
+ * and stores).  Its measured rate is the achievable HBM bandwidth the hopping
+ * matrix is compared with, and its hardware counters calibrate the measured
+ * traffic of the other kernels. */
+tmh_status tmh_stream_copy(tmh_lattice* lat, void* dst, const void* src, size_t nbytes);
 
 /* Launch timing.  Section 3 of the paper measures where the hopping matrix
  * and the solver spend their time; this is the device-side equivalent.  With

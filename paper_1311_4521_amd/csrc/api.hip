@@ -371,6 +371,9 @@ tmh_status tmh_lattice_create(tmh_lattice** out, const int dims[4], int device, 
         V *= dims[m];
         if (V > ((int64_t)1 << 30)) return TMH_ERR_GEOMETRY;
     }
+    // every component array (S FP64 complexes) must stay below 4 GiB: the
+    // kernels address it through 32-bit buffer offsets
+    if ((V / 2 + 63) / 64 * 64 * 16 >= ((int64_t)1 << 32)) return TMH_ERR_GEOMETRY;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TMH_ERR_HIP;
     DeviceGuard guard(device);
@@ -547,6 +550,15 @@ tmh_status tmh_scalar_prod_r(tmh_lattice* l, double* result, const void* a, cons
 
 tmh_status tmh_norm2(tmh_lattice* l, double* result, const void* a, tmh_prec prec) {
     return tmh_scalar_prod_r(l, result, a, a, prec);
+}
+
+tmh_status tmh_stream_copy(tmh_lattice* l, void* dst, const void* src, size_t nbytes) {
+    TMH_TRY(check_lat(l));
+    if (!dst || !src || nbytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0) return TMH_ERR_ARG;
+    if (overlap(dst, nbytes, src, nbytes)) return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    TMH_TRY_HIP(tmh::launch_stream_copy(dst, src, nbytes, l->stream));
+    return TMH_OK;
 }
 
 tmh_status tmh_profile_enable(tmh_lattice* l, int on) {

@@ -197,7 +197,33 @@ __global__ void __launch_bounds__(kBlock) zero_kernel(typename Word<R>::T* __res
     }
 }
 
+// dst = src for n 16-byte words, 4 words per thread per pass, non-temporal.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(kBlock) stream_copy_kernel(u32x4* __restrict__ dst, const u32x4* __restrict__ src,
+                                                             int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock * 4;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock * 4 + threadIdx.x; base < n; base += stride) {
+        u32x4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (base + k * kBlock < n) v[k] = __builtin_nontemporal_load(src + base + k * kBlock);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (base + k * kBlock < n) __builtin_nontemporal_store(v[k], dst + base + k * kBlock);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t nbytes, hipStream_t s) {
+    const int64_t n = (int64_t)(nbytes / 16);
+    if (n == 0) return hipSuccess;
+    int64_t nb = (n + kBlock * 4 - 1) / (kBlock * 4);
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, (u32x4*)dst,
+                       (const u32x4*)src, n);
+    return hipGetLastError();
+}
 
 int blas_blocks(const Geo& g) {
     const int nb = (g.Vh + kBlock - 1) / kBlock;

@@ -60,6 +60,62 @@ __device__ __forceinline__ void st(typename Word<R>::T* __restrict__ p, int64_t 
     p[k] = w;
 }
 
+// Raw buffer access to one component array: the descriptor (base, size) is
+// uniform and lives in SGPRs, the per-lane byte offset is one VGPR.  Offsets
+// at or beyond `nbytes` read as zero and drop stores (hardware range check).
+// Word 3 = 0x00020000 is the raw-buffer format for gfx9-family parts.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nbytes, 0x00020000);
+}
+
+template <typename R> struct BufIO;
+template <> struct BufIO<double> {
+    template <int AUX>
+    __device__ static __forceinline__ double2 load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX);
+        double2 w;
+        __builtin_memcpy(&w, &v, sizeof w);
+        return w;
+    }
+    template <int AUX>
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned off, double2 w) {
+        unsigned int __attribute__((ext_vector_type(4))) v;
+        __builtin_memcpy(&v, &w, sizeof w);
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, AUX);
+    }
+};
+template <> struct BufIO<float> {
+    template <int AUX>
+    __device__ static __forceinline__ float2 load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX);
+        float2 w;
+        __builtin_memcpy(&w, &v, sizeof w);
+        return w;
+    }
+    template <int AUX>
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned off, float2 w) {
+        unsigned int __attribute__((ext_vector_type(2))) v;
+        __builtin_memcpy(&v, &w, sizeof w);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, AUX);
+    }
+};
+
+// Complex element `i` of the component array starting at `base` (S words).
+template <typename R, int AUX = 0>
+__device__ __forceinline__ cx<R> bload(const typename Word<R>::T* base, int S, int i) {
+    const unsigned wb = sizeof(typename Word<R>::T);
+    const auto w = BufIO<R>::template load<AUX>(buf_rsrc(base, (unsigned)S * wb), (unsigned)i * wb);
+    return {w.x, w.y};
+}
+template <typename R, int AUX = 0>
+__device__ __forceinline__ void bstore(typename Word<R>::T* base, int S, int i, cx<R> v) {
+    const unsigned wb = sizeof(typename Word<R>::T);
+    typename Word<R>::T w;
+    w.x = v.re;
+    w.y = v.im;
+    BufIO<R>::template store<AUX>(buf_rsrc(base, (unsigned)S * wb), (unsigned)i * wb, w);
+}
+
 // Lattice extents and strides as seen by the kernels.
 struct Geo {
     int L[4];   // T, LX, LY, LZ
@@ -93,19 +149,20 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return x * q + (x < r ? x : r) + k;
 }
 
-// Sum over a workgroup of kBlock threads, in a fixed order; the result is
-// valid in thread 0.
+// Sum over a workgroup of NT threads (a multiple of 64), in a fixed order;
+// the result is valid in thread 0.  Call at most once per kernel.
+template <int NT = kBlock>
 __device__ __forceinline__ double block_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    __shared__ double wsum[kBlock / 64];
+    __shared__ double wsum[NT / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) wsum[wid] = v;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += wsum[w];
+        for (int w = 0; w < NT / 64; ++w) s += wsum[w];
     }
     return s;
 }

@@ -69,6 +69,8 @@ template <typename R>
 hipError_t launch_copy(typename Word<R>::T* dst, const typename Word<R>::T* src, const Geo& g, hipStream_t s);
 template <typename R>
 hipError_t launch_zero(typename Word<R>::T* dst, const Geo& g, hipStream_t s);
+// Streaming device copy of nbytes (a multiple of 16): bandwidth reference.
+hipError_t launch_stream_copy(void* dst, const void* src, size_t nbytes, hipStream_t s);
 // Copies src to dst and resets the CG scalars: scal[kRR] = |src|^2 from the
 // given partials, flags = {0, 0}.
 hipError_t launch_cg_init(double* scal, const double* partial, int n, int* flags, double stop,

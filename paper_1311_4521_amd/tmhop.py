@@ -76,6 +76,7 @@ _sig("tmh_cg_solve", _I, [_P, _P, _P, _P, _D, _D, _P, _D, _I, _I, ctypes.POINTER
 _sig("tmh_hop_force", _I, [_P, _I, _P, _P, _P, _P, _D, _P, _D])
 _sig("tmh_scalar_prod_r", _I, [_P, ctypes.POINTER(_D), _P, _P, _I])
 _sig("tmh_norm2", _I, [_P, ctypes.POINTER(_D), _P, _I])
+_sig("tmh_stream_copy", _I, [_P, _P, _P, _S])
 _sig("tmh_profile_enable", _I, [_P, _I])
 _sig("tmh_profile_read", _I, [_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D)])
 _sig("tmh_status_string", ctypes.c_char_p, [_I])
@@ -84,7 +85,7 @@ EXPORTED = ("tmh_lattice_create", "tmh_lattice_destroy", "tmh_lattice_set_stream
             "tmh_half_volume", "tmh_site_stride", "tmh_spinor_bytes", "tmh_gauge_bytes",
             "tmh_gauge_import", "tmh_spinor_import", "tmh_spinor_export", "tmh_hop_apply",
             "tmh_qtm_apply", "tmh_cg_solve", "tmh_hop_force", "tmh_scalar_prod_r", "tmh_norm2",
-            "tmh_profile_enable", "tmh_profile_read", "tmh_status_string")
+            "tmh_stream_copy", "tmh_profile_enable", "tmh_profile_read", "tmh_status_string")
 
 
 class TmhError(RuntimeError):
@@ -301,6 +302,16 @@ def norm2(lat: Lattice, a, prec=F64) -> float:
     lat._sync_stream()
     _check(_lib.tmh_norm2(lat.handle, ctypes.byref(r), a.data_ptr(), p), "tmh_norm2")
     return r.value
+
+
+def stream_copy(lat: Lattice, dst, src):
+    """dst = src (same byte size, torch tensors) through the streaming copy
+    kernel: the achievable-bandwidth reference."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("stream_copy needs buffers of equal size")
+    lat._sync_stream()
+    _check(_lib.tmh_stream_copy(lat.handle, dst.data_ptr(), src.data_ptr(), n), "tmh_stream_copy")
 
 
 PROFILE_KINDS = 6
