@@ -19,7 +19,6 @@ and the CPU oracle is timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,8 +33,6 @@ FLOP_PER_SITE = 1320
 BYTES_PER_SITE_F64 = 1536          # 8 links x 144 B + input spinor 192 B + output 192 B
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_f64_32x32x32x64_traffic.json")
-HOP_SOURCES = [os.path.join(ROOT, "paper_1311_4521_amd", "csrc", f)
-               for f in ("hop.hip", "common.h", "kernels.h")]
 
 WORKLOADS = {
     "qtm32": dict(dims=(64, 32, 32, 32), kappa=0.1632, mt=0.0013, seed=2,
@@ -48,14 +45,6 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def hop_source_hash():
-    h = hashlib.sha256()
-    for f in HOP_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(n_sites):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary, or None if absent or taken on other code."""
@@ -64,9 +53,10 @@ def measured_traffic(n_sites):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
+    from paper_1311_4521_amd.rocprof_summary import hop_source_hash
     if t.get("source_hash") != hop_source_hash() or t.get("sites") != n_sites:
         return None
-    return t.get("bytes_per_launch")
+    return round(t.get("bytes_per_launch"), 0)
 
 
 def cpu_baseline(dims, U, psi, kappa, theta, budget_s):
@@ -167,6 +157,24 @@ def main():
         if n:
             per_kind[names[k]] = {"launches": n, "avg_us": round(ms * 1e3 / n, 2)}
 
+    # ---- achievable-bandwidth reference: streaming copy of the hop's bytes
+    half = BYTES_PER_SITE_F64 * Vh // 2 // 16 * 16
+    src = torch.empty(half // 8, dtype=torch.float64, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        tmhop.stream_copy(lat, dst, src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(20):
+        tmhop.stream_copy(lat, dst, src)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_us = ev0.elapsed_time(ev1) * 1e3 / 20
+    copy_gbs = 2 * half / (copy_us * 1e-6) / 1e9
+    del src, dst
+    log(f"streaming copy reference: {copy_gbs:.0f} GB/s ({2 * half} bytes moved per copy)")
+
     # ---- mixed precision beside it
     mixed = []
     mixed_it = mixed_res = None
@@ -184,7 +192,7 @@ def main():
     d = (x - x64).double()
     mixed_vs_fp64 = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(x64))
     fp64_ms = dt * 1e3 / args.steps
-    log(f"mixed solve: {mixed_ms:.2f} ms, {mixed_it} inner iterations")
+    log(f"mixed solve: {mixed_ms} ms, {mixed_it} inner iterations")
 
     traffic = measured_traffic(Vh)
     line = {
@@ -213,6 +221,8 @@ def main():
             "bytes_per_site": BYTES_PER_SITE_F64,
             "avg_us": round(hop_us, 2),
             "launches": n0,
+            "copy_reference_GBs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "hop_gflops": round(FLOP_PER_SITE * Vh / (hop_us * 1e-6) / 1e9, 1),
         "kernels": per_kind,
