@@ -32,12 +32,17 @@ METRIC = "Dslash GFlop/s + % HBM roofline at 32^3x64; mixed vs FP64 CG time to 1
 FLOP_PER_SITE = 1320
 BYTES_PER_SITE_F64 = 1536          # 8 links x 144 B + input spinor 192 B + output 192 B
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_f64_32x32x32x64_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_f64_32x32x32x64_traffic.json")  # 32^3x64 only
 
 WORKLOADS = {
-    "qtm32": dict(dims=(64, 32, 32, 32), kappa=0.1632, mt=0.0013, seed=2,
+    "qtm32": dict(dims=(64, 32, 32, 32), kappa=0.1632, mt=0.0013, seed=2, links="haar",
                   label="Qtm + FP64 CG to 1e-10 on 32^3x64, Haar SU(3) links, "
                         "kappa=0.1632, 2*kappa*mu=0.0013, antiperiodic time"),
+    # the mixed-precision workload: smoothed links U = exp(i 0.3 H); the
+    # paper's 48^3x96 inversion fixes no kappa or mu, the 32^3x64 values are reused
+    "mixed48": dict(dims=(96, 48, 48, 48), kappa=0.1632, mt=0.0013, seed=3, links="smooth",
+                    label="FP64 CG vs FP32-inner defect-correction CG to 1e-10 on 48^3x96, "
+                          "links exp(0.3 i H), kappa=0.1632, 2*kappa*mu=0.0013, antiperiodic time"),
 }
 
 
@@ -108,8 +113,11 @@ def main():
     theta = (1.0, 0.0, 0.0, 0.0)
     torch.cuda.set_device(0)
 
-    log(f"generating fields {dims} (seed {w['seed']})")
-    U = fieldgen.gauge_haar(dims, w["seed"])
+    log(f"generating fields {dims} (seed {w['seed']}, {w['links']} links)")
+    if w["links"] == "haar":
+        U = fieldgen.gauge_haar(dims, w["seed"])
+    else:
+        U = fieldgen.gauge_smooth(dims, w["seed"], 0.3)
     Vh = int(np.prod(dims)) // 2
     b = fieldgen.spinor_gauss(Vh, 100 + w["seed"])
 

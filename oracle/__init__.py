@@ -53,11 +53,13 @@ def lib():
         L.orc_cg.argtypes = [P, P, P, P, D, D, P, D, I, P, P]
         L.orc_re_dot.argtypes = [P, P, ctypes.c_int64]
         L.orc_re_dot.restype = D
+        L.orc_hop_force.argtypes = [P, I, P, P, P, P, D, P, D, I]
+        L.orc_qtm_force.argtypes = [P, P, P, P, P, D, D, P, I, D, I]
         L.orc_gamma.argtypes = [I, P]
         L.orc_gamma.restype = None
         L.orc_num_threads.restype = I
         for name in ("orc_hop", "orc_hop_sites", "orc_hop_full", "orc_eo_sites", "orc_qtm",
-                     "orc_cg"):
+                     "orc_cg", "orc_hop_force", "orc_qtm_force"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -176,3 +178,39 @@ def re_dot(a, b) -> float:
     a = _c128(a)
     b = _c128(b)
     return lib().orc_re_dot(_p(a), _p(b), a.size)
+
+
+FORCE_KINDS = {"su3": 0, "euclid": 1}
+
+
+def hop_force(dims, direction, gauge, X, Y, kappa, theta, coeff=1.0, kind="su3", out=None):
+    """Link derivative of L = Re <X, H Y> ('eo': X even, Y odd; 'oe': X odd,
+    Y even): returns out + coeff * TA(M) (kind 'su3') or + coeff * G with
+    dL = Re sum conj(G) dU for U a free complex matrix (kind 'euclid'),
+    shape [4][V][3][3]."""
+    d = {"eo": 0, "oe": 1}[direction]
+    gauge = _c128(gauge)
+    X = _c128(X)
+    Y = _c128(Y)
+    if out is None:
+        out = np.zeros_like(gauge)
+    else:
+        out = _c128(out).copy()
+    _check(lib().orc_hop_force(_p(_dims(dims)), d, _p(out), _p(gauge), _p(X), _p(Y), float(kappa),
+                               _p(_theta(theta)), float(coeff), FORCE_KINDS[kind]), "hop_force")
+    return out
+
+
+def qtm_force(dims, gauge, chi, psi, kappa, mu, theta, sign=+1, coeff=1.0, kind="su3", out=None):
+    """Link derivative of L = Re <chi, Qhat(sign) psi>."""
+    gauge = _c128(gauge)
+    chi = _c128(chi)
+    psi = _c128(psi)
+    if out is None:
+        out = np.zeros_like(gauge)
+    else:
+        out = _c128(out).copy()
+    _check(lib().orc_qtm_force(_p(_dims(dims)), _p(out), _p(gauge), _p(chi), _p(psi), float(kappa),
+                               float(mu), _p(_theta(theta)), int(sign), float(coeff),
+                               FORCE_KINDS[kind]), "qtm_force")
+    return out

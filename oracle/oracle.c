@@ -31,6 +31,15 @@
  *   mass      Mhat(s) = A(s) - H_oe A(s)^-1 H_eo on odd fields,
  *             Qhat(s) = gamma_5 Mhat(s).  A(s)^-1 = (1 - i s mt gamma_5)/(1 + mt^2)
  *             (gamma_5^2 = 1).
+ *   Force     for L = Re <X, H Y>, a link varied as U -> exp(t Z) U with Z
+ *             anti-Hermitian traceless changes L by t tr(Z TA(M)), where
+ *             L = Re tr(U W) over the terms containing the link and M is the
+ *             derivative matrix of each term (see link_matrix below);
+ *             TA(M) = (M - M^+)/2 - tr(M - M^+)/6.  The Euclidean gradient
+ *             G with dL = Re sum conj(G) dU, for U taken as a free complex
+ *             matrix, is W^+ for a forward and W for a backward term.  The
+ *             paper only names the "fermionic derivative" (Section 2, race
+ *             conditions).
  *   CG        conjugate gradient on Qhat(+)^dagger Qhat(+) = Qhat(-) Qhat(+),
  *             stopped when |r|^2 <= tol^2 |b|^2, then the true residual
  *             b - A x is recomputed; if it is above tol, CG restarts from x
@@ -436,6 +445,144 @@ int orc_cg(const int dims[4], double* xd, const double* bd, const double* gauge,
     free(r); free(p); free(q); free(tmp);
     if (st) return st;
     return converged ? 0 : 1;
+}
+
+/* ---------------------------------------------------------------- force */
+
+/* The derivative matrix of the one term of L = Re <X, H Y> that contains
+ * the link U_mu(l).  H holds each link in exactly one term:
+ *   l on the output parity: the forward term at x = l,
+ *     Re X(x)^+ kappa eta+ (1 - gamma_mu) U Y(x+mu) = Re tr(U W),
+ *     W = kappa eta+ sum_s phi_s X(x)_s^+, phi = (1 - gamma_mu) Y(x+mu);
+ *     with U -> exp(tZ) U:  dL/dt = Re tr(Z U W)       -> M = U W;
+ *     as a function of the free complex U, dL = Re sum conj(W^+) dU.
+ *   l on the input parity: the backward term at x = l + mu,
+ *     Re X(x)^+ kappa eta- (1 + gamma_mu) U^+ Y(l) = Re tr(U^+ W),
+ *     W = kappa eta- sum_s phi_s X(x)_s^+, phi = (1 + gamma_mu) Y(l);
+ *     U^+ -> U^+ exp(-tZ): dL/dt = -Re tr(Z W U^+)     -> M = -W U^+;
+ *     as a function of the free complex U, dL = Re sum conj(W) dU.
+ * X and Y are even-odd fields.  Returns 1 for a forward term. */
+static int link_matrix(const geom* g, int64_t l, int mu, int pout, cplx M[3][3], cplx W[3][3],
+                       const cplx* U, const cplx* X, const cplx* Y, double kappa,
+                       const double theta[4])
+{
+    int c[4];
+    coords(g, l, c);
+    const int p = (c[0] + c[1] + c[2] + c[3]) & 1;
+    const int forward = p == pout;
+    int wrapped;
+    const int64_t nb = neighbour(g, c, mu, +1, &wrapped); /* both cases: the site l + mu */
+    cplx eta = 1.0;
+    if (wrapped) eta = cexp(I * ((forward ? 1 : -1) * M_PI * theta[mu]));
+    const cplx* xs = X + 12 * (int64_t)g->eo_of_lex[forward ? l : nb];
+    const cplx* ys = Y + 12 * (int64_t)g->eo_of_lex[forward ? nb : l];
+    const double sg = forward ? -1.0 : 1.0; /* 1 - gamma or 1 + gamma */
+    cplx phi[4][3];
+    for (int s = 0; s < 4; ++s)
+        for (int a = 0; a < 3; ++a) {
+            cplx sum = 0;
+            for (int r = 0; r < 4; ++r) sum += ((s == r ? 1.0 : 0.0) + sg * GAM[mu][s][r]) * ys[3 * r + a];
+            phi[s][a] = sum;
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            cplx sum = 0;
+            for (int s = 0; s < 4; ++s) sum += phi[s][a] * conj(xs[3 * s + b]);
+            W[a][b] = kappa * eta * sum;
+        }
+    const cplx* u = U + 9 * (mu * g->V + l);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            cplx sum = 0;
+            for (int k = 0; k < 3; ++k)
+                sum += forward ? u[3 * a + k] * W[k][b] : -W[a][k] * conj(u[3 * b + k]);
+            M[a][b] = sum;
+        }
+    return forward;
+}
+
+/* Adds to out[mu][l]: kind 0: coeff * TA(M) (the su(3) force); kind 1:
+ * coeff * (W^+ or W) (the Euclidean gradient of a forward or backward term). */
+static void add_projected(const geom* g, int64_t l, int mu, cplx M[3][3], cplx W[3][3], int forward,
+                          cplx* out, double coeff, int kind)
+{
+    cplx* f = out + 9 * (mu * g->V + l);
+    if (kind == 0) {
+        cplx A[3][3];
+        cplx tr = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) A[a][b] = 0.5 * (M[a][b] - conj(M[b][a]));
+        for (int a = 0; a < 3; ++a) tr += A[a][a];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) f[3 * a + b] += coeff * (A[a][b] - (a == b ? tr / 3.0 : 0.0));
+    } else {
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) f[3 * a + b] += coeff * (forward ? conj(W[b][a]) : W[a][b]);
+    }
+}
+
+/* out[4][V][3][3] += coeff * P(dL/dU) for L = Re <X, H Y>; dir 0: H_eo
+ * (X even, Y odd), dir 1: H_oe (X odd, Y even); kind as for add_projected. */
+int orc_hop_force(const int dims[4], int dir, double* out, const double* gauge, const double* X,
+                  const double* Y, double kappa, const double theta[4], double coeff, int kind)
+{
+    if ((dir != 0 && dir != 1) || (kind != 0 && kind != 1)) return -1;
+    gam_init();
+    geom g;
+    int st = geom_init(&g, dims);
+    if (st) return st;
+    const int pout = dir == 0 ? 0 : 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t l = 0; l < g.V; ++l)
+        for (int mu = 0; mu < 4; ++mu) {
+            cplx M[3][3], W[3][3];
+            const int fwd = link_matrix(&g, l, mu, pout, M, W, (const cplx*)gauge, (const cplx*)X,
+                                        (const cplx*)Y, kappa, theta);
+            add_projected(&g, l, mu, M, W, fwd, (cplx*)out, coeff, kind);
+        }
+    geom_free(&g);
+    return 0;
+}
+
+/* out += coeff * P(dL/dU) for L = Re <chi, Qhat(sign) psi>.  With
+ * Qhat = gamma_5 [A - H_oe A^-1 H_eo],
+ *   dL = -Re <gamma_5 chi, dH_oe A^-1 H_eo psi> - Re <X2, dH_eo psi>,
+ *   X2 = (A^-1)^+ H_oe^+ gamma_5 chi = (A^+)^-1 gamma_5 H_eo chi
+ * (gamma_5-hermiticity H_oe^+ = gamma_5 H_eo gamma_5). */
+int orc_qtm_force(const int dims[4], double* out, const double* gauge, const double* chi,
+                  const double* psi, double kappa, double mu, const double theta[4], int sign,
+                  double coeff, int kind)
+{
+    if (sign != 1 && sign != -1) return -1;
+    geom g;
+    int st = geom_init(&g, dims);
+    if (st) return st;
+    const int64_t Vh = g.Vh;
+    geom_free(&g);
+    cplx* te = malloc(sizeof(cplx) * 12 * Vh);
+    cplx* x1 = malloc(sizeof(cplx) * 12 * Vh);
+    if (!te || !x1) { free(te); free(x1); return -2; }
+    const double mt = 2.0 * kappa * mu * sign;
+    const double D = 1.0 + mt * mt;
+    /* first term: X = gamma_5 chi (odd), Y = A^-1 H_eo psi (even), through H_oe */
+    st = orc_hop(dims, 0, (double*)te, gauge, psi, kappa, theta);
+    if (!st) {
+        spin_lincomb_g5(te, te, Vh, 1.0 / D, -I * mt / D);
+        spin_lincomb_g5(x1, (const cplx*)chi, Vh, 0.0, 1.0);
+        st = orc_hop_force(dims, 1, out, gauge, (const double*)x1, (const double*)te, kappa, theta,
+                           -coeff, kind);
+    }
+    /* second term: X = (A^+)^-1 gamma_5 H_eo chi (even), Y = psi (odd), through H_eo;
+     * (A^+)^-1 = (1 + i mt gamma_5)/D */
+    if (!st) st = orc_hop(dims, 0, (double*)te, gauge, chi, kappa, theta);
+    if (!st) {
+        spin_lincomb_g5(te, te, Vh, 0.0, 1.0);
+        spin_lincomb_g5(te, te, Vh, 1.0 / D, I * mt / D);
+        st = orc_hop_force(dims, 0, out, gauge, (const double*)te, psi, kappa, theta, -coeff, kind);
+    }
+    free(te);
+    free(x1);
+    return st;
 }
 
 int orc_num_threads(void)

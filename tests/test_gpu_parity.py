@@ -278,3 +278,36 @@ def test_full_size_32x32x32x64_hop_and_qtm():
     tm.qtm_apply(lat, out, G, x, kappa, mu, THETA_AP, +1)
     ref = oracle.qtm(dims, U, psi, kappa, mu, THETA_AP, +1)
     assert site_rel_err(to_host(tm.spinor_export(lat, out)), ref) <= 1e-13
+
+
+@pytest.mark.slow
+def test_full_size_48x48x48x96_mixed_precision():
+    """48^3x96 with smoothed links: FP32 hop on sampled sites against the
+    FP64 oracle, and the FP32-inner defect-correction CG reaching a 1e-10
+    true residual, checked with the oracle's operator."""
+    dims, kappa, mt = (96, 48, 48, 48), 0.1632, 0.0013
+    mu = mu_of(kappa, mt)
+    U = fieldgen.gauge_smooth(dims, fieldgen.SEEDS["mixed48"], 0.3)
+    Vh = int(np.prod(dims)) // 2
+    b = fieldgen.spinor_gauss(Vh, 100 + fieldgen.SEEDS["mixed48"])
+    lat = tm.Lattice(dims)
+    G32 = tm.gauge_import(lat, U, tm.F32)
+    x32 = tm.spinor_import(lat, b, tm.F32)
+    out = lat.new_spinor(tm.F32)
+    g = fieldgen.rng(31)
+    slab = dims[1] * dims[2] * dims[3] // 2
+    sites = np.unique(np.concatenate([np.arange(slab), np.arange(Vh - slab, Vh),
+                                      g.integers(0, Vh, 20000)]))
+    tm.hop_apply(lat, "oe", out, G32, x32, kappa, THETA_AP, tm.F32)
+    got = to_host(tm.spinor_export(lat, out, tm.F32))[sites]
+    ref = oracle.hop_sites(dims, "oe", sites, U, b, kappa, THETA_AP)
+    assert site_rel_err(got, ref) <= 1e-5
+    del G32, x32, out
+    G = tm.gauge_import(lat, U)
+    tb = tm.spinor_import(lat, b)
+    x = lat.new_spinor()
+    it, res, ok = tm.cg_solve(lat, x, tb, G, kappa, mu, THETA_AP, 1e-10, 5000, tm.F32)
+    assert ok and res <= 1e-10
+    xh = to_host(tm.spinor_export(lat, x))
+    r = b - oracle.normal(dims, U, xh, kappa, mu, THETA_AP)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.05e-10
