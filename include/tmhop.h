@@ -143,11 +143,33 @@ tmh_status tmh_cg_solve(tmh_lattice* lat, void* x, const void* b, const void* ga
                         double kappa, double mu, const double theta[4], double rel_tol,
                         int max_iter, tmh_prec inner, int* iters, double* true_rel_res);
 
-/* Gauge-link derivative ("fermionic derivative", Section 2, race conditions):
- * not built in this library yet; returns TMH_ERR_UNSUPPORTED. */
-tmh_status tmh_hop_force(tmh_lattice* lat, tmh_dir dir, double* force, const void* gauge,
+/* Gauge-link derivative, the paper's "fermionic derivative" (Section 2,
+ * "Race conditions and Memory Locking", which updates it with atomics; here
+ * every link has one writer).  For L = Re <left, H right> with H = H_eo
+ * (TMH_EO: left even, right odd) or H_oe (TMH_OE: left odd, right even), every
+ * link U = U_mu(x) of the lattice gets force[link] += coeff * P(link), where
+ *   TMH_FORCE_SU3:    P = TA(M) = (M - M^+)/2 - tr(M - M^+)/6, the su(3)
+ *                     force: under U -> exp(tZ) U, dL/dt = tr(Z TA(M));
+ *   TMH_FORCE_EUCLID: P = G with dL = Re sum conj(G) dU for U a free complex
+ *                     matrix (the gradient torch expects).
+ * force, gauge, left and right are FP64 internal-layout buffers (force in the
+ * gauge layout, tmh_gauge_bytes(TMH_F64)); force must not overlap the
+ * inputs.  Enqueued on the handle's stream. */
+typedef enum { TMH_FORCE_SU3 = 0, TMH_FORCE_EUCLID = 1 } tmh_force_kind;
+tmh_status tmh_hop_force(tmh_lattice* lat, tmh_dir dir, void* force, const void* gauge,
                          const void* left, const void* right, double kappa,
-                         const double theta[4], double coeff);
+                         const double theta[4], double coeff, tmh_force_kind kind);
+
+/* The same for L = Re <chi, Qhat(sign) psi> (chi, psi odd, FP64): two
+ * hopping-matrix launches into the handle's even scratch and two force
+ * launches.  For L = |Qhat psi|^2 pass chi = 2 Qhat psi.  The psi-gradient
+ * of L is Qhat(-sign) chi (tmh_qtm_apply). */
+tmh_status tmh_qtm_force(tmh_lattice* lat, void* force, const void* gauge, const void* chi,
+                         const void* psi, double kappa, double mu, const double theta[4],
+                         int sign, double coeff, tmh_force_kind kind);
+
+/* Internal gauge layout (precision prec) -> canonical FP64 [4][V][3][3]. */
+tmh_status tmh_gauge_export(tmh_lattice* lat, double* dst, const void* src, tmh_prec prec);
 
 /* scalar_prod_r (Section 3): *result = Re <a, b> = Re sum conj(a) b over one
  * parity, in FP64 with a deterministic two-pass reduction.  Blocks. */

@@ -4,10 +4,11 @@ The computation lives in ``libtmhop.so`` (hand-written HIP for gfx950, C-ABI
 in ``include/tmhop.h``); ``tmhop`` is its ctypes binding.
 """
 
-from .tmhop import (EO, F32, F64, OE, Lattice, TmhError, cg_solve, gauge_import, hop_apply,
-                    hop_force, lattice_create, norm2, qtm_apply, scalar_prod_r, spinor_export,
-                    spinor_import, status_string)
+from .tmhop import (EO, F32, F64, OE, Lattice, TmhError, cg_solve, gauge_export, gauge_import,
+                    hop_apply, hop_force, lattice_create, norm2, qtm_apply, qtm_force,
+                    scalar_prod_r, spinor_export, spinor_import, status_string)
 
 __all__ = ["EO", "OE", "F64", "F32", "Lattice", "TmhError", "lattice_create", "gauge_import",
-           "spinor_import", "spinor_export", "hop_apply", "qtm_apply", "cg_solve", "hop_force",
+           "spinor_import", "spinor_export", "gauge_export", "hop_apply", "qtm_apply", "cg_solve",
+           "hop_force", "qtm_force",
            "scalar_prod_r", "norm2", "status_string"]

@@ -27,6 +27,7 @@ struct tmh_lattice {
     double* h_scal;         // pinned host mirror of scal
     int* h_flags;           // pinned host mirror of flags
     void* even[2];          // intermediate even field per precision (Qtm)
+    void* even2;            // second FP64 even field (force chain)
     double2* v64[4];        // FP64 CG vectors r, p, v, q
     float2* v32[5];         // FP32 inner CG vectors r, p, v, q, d
     float2* gauge32;        // FP32 copy of the links for the mixed-precision inner solve
@@ -187,6 +188,32 @@ tmh_status qtm_launch(tmh_lattice* l, void* out, const void* gauge, const void* 
     b.d_im[1] = (R)mt;
     TMH_TRY_HIP(hop_launch<R>(l, b, partial ? 2 : 1));
     return TMH_OK;
+}
+
+// force += coeff * P(dRe<X, H Y>/dU), X on parity pout taken as c_{s/2} X_s.
+hipError_t force_launch(tmh_lattice* l, int pout, void* force, const void* gauge, const void* X, const void* Y,
+                        double kappa, const double theta[4], double coeff, int kind, double cu_re, double cu_im,
+                        double cd_re, double cd_im) {
+    tmh::ForceArgs f;
+    memset(&f, 0, sizeof f);
+    f.force = (double2*)force;
+    f.gauge = (const double2*)gauge;
+    f.X = (const double2*)X;
+    f.Y = (const double2*)Y;
+    f.g = l->g;
+    f.pout = pout;
+    f.kind = kind;
+    f.kappa = kappa;
+    f.coeff = coeff;
+    for (int m = 0; m < 4; ++m) {
+        f.ph_re[m] = cos(M_PI * theta[m]);
+        f.ph_im[m] = sin(M_PI * theta[m]);
+    }
+    f.cx_re[0] = cu_re;
+    f.cx_im[0] = cu_im;
+    f.cx_re[1] = cd_re;
+    f.cx_im[1] = cd_im;
+    return tmh::launch_force(f, l->stream);
 }
 
 tmh_status check_lat(const tmh_lattice* l) { return l ? TMH_OK : TMH_ERR_ARG; }
@@ -415,6 +442,7 @@ void tmh_lattice_destroy(tmh_lattice* l) {
     if (l->h_scal) (void)hipHostFree(l->h_scal);
     if (l->h_flags) (void)hipHostFree(l->h_flags);
     for (void* p : l->even) (void)hipFree(p);
+    (void)hipFree(l->even2);
     for (void* p : l->v64) (void)hipFree(p);
     for (void* p : l->v32) (void)hipFree(p);
     (void)hipFree(l->gauge32);
@@ -534,10 +562,70 @@ tmh_status tmh_cg_solve(tmh_lattice* l, void* x, const void* b, const void* gaug
     return st;
 }
 
-tmh_status tmh_hop_force(tmh_lattice* l, tmh_dir, double*, const void*, const void*, const void*, double,
-                         const double*, double) {
+tmh_status tmh_hop_force(tmh_lattice* l, tmh_dir dir, void* force, const void* gauge, const void* left,
+                         const void* right, double kappa, const double theta[4], double coeff,
+                         tmh_force_kind kind) {
     TMH_TRY(check_lat(l));
-    return TMH_ERR_UNSUPPORTED;
+    TMH_TRY(check_theta(theta));
+    if (dir != TMH_EO && dir != TMH_OE) return TMH_ERR_ARG;
+    if (kind != TMH_FORCE_SU3 && kind != TMH_FORCE_EUCLID) return TMH_ERR_ARG;
+    if (!force || !gauge || !left || !right || !isfinite(kappa) || !isfinite(coeff)) return TMH_ERR_ARG;
+    const size_t gb = gauge_bytes(l, TMH_F64), sb = spinor_bytes(l, TMH_F64);
+    if (overlap(force, gb, gauge, gb) || overlap(force, gb, left, sb) || overlap(force, gb, right, sb))
+        return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    TMH_TRY_HIP(force_launch(l, dir == TMH_EO ? 0 : 1, force, gauge, left, right, kappa, theta, coeff, kind,
+                             1.0, 0.0, 1.0, 0.0));
+    return TMH_OK;
+}
+
+tmh_status tmh_qtm_force(tmh_lattice* l, void* force, const void* gauge, const void* chi, const void* psi,
+                         double kappa, double mu, const double theta[4], int sign, double coeff,
+                         tmh_force_kind kind) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_theta(theta));
+    if (sign != 1 && sign != -1) return TMH_ERR_ARG;
+    if (kind != TMH_FORCE_SU3 && kind != TMH_FORCE_EUCLID) return TMH_ERR_ARG;
+    if (!force || !gauge || !chi || !psi || !isfinite(kappa) || !isfinite(mu) || !isfinite(coeff))
+        return TMH_ERR_ARG;
+    const size_t gb = gauge_bytes(l, TMH_F64), sb = spinor_bytes(l, TMH_F64);
+    if (overlap(force, gb, gauge, gb) || overlap(force, gb, chi, sb) || overlap(force, gb, psi, sb))
+        return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    void* te;
+    TMH_TRY(even_scratch(l, TMH_F64, &te));
+    TMH_TRY(ensure(&l->even2, spinor_bytes(l, TMH_F64)));
+    const double mt = 2.0 * kappa * mu * sign;
+    const double D = 1.0 + mt * mt;
+    // te = A^-1 H_eo psi; force -= coeff * dRe<gamma_5 chi, H_oe te>
+    HopArgs<double> a = hop_args<double>(l, 0, te, gauge, psi, theta);
+    a.c_re[0] = kappa / D;
+    a.c_im[0] = -kappa * mt / D;
+    a.c_re[1] = kappa / D;
+    a.c_im[1] = kappa * mt / D;
+    TMH_TRY_HIP(hop_launch<double>(l, a, 0));
+    TMH_TRY_HIP(force_launch(l, 1, force, gauge, chi, te, kappa, theta, -coeff, kind, 1.0, 0.0, -1.0, 0.0));
+    // w = H_eo chi; force -= coeff * dRe<(A^+)^-1 gamma_5 w, H_eo psi>,
+    // (A^+)^-1 gamma_5 = diag((1 + i mt)/D, -(1 - i mt)/D) on upper/lower spins
+    HopArgs<double> b = hop_args<double>(l, 0, l->even2, gauge, chi, theta);
+    b.c_re[0] = b.c_re[1] = kappa;
+    TMH_TRY_HIP(hop_launch<double>(l, b, 0));
+    TMH_TRY_HIP(force_launch(l, 0, force, gauge, l->even2, psi, kappa, theta, -coeff, kind, 1.0 / D, mt / D,
+                             -1.0 / D, mt / D));
+    return TMH_OK;
+}
+
+tmh_status tmh_gauge_export(tmh_lattice* l, double* dst, const void* src, tmh_prec prec) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(prec));
+    if (!dst || !src) return TMH_ERR_ARG;
+    if (overlap(dst, (size_t)2 * l->g.Vh * 4 * 9 * 16, src, gauge_bytes(l, prec))) return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    if (prec == TMH_F64)
+        TMH_TRY_HIP(tmh::launch_gauge_export<double>(dst, (const double2*)src, l->g, l->stream));
+    else
+        TMH_TRY_HIP(tmh::launch_gauge_export<float>(dst, (const float2*)src, l->g, l->stream));
+    return TMH_OK;
 }
 
 tmh_status tmh_scalar_prod_r(tmh_lattice* l, double* result, const void* a, const void* b, tmh_prec prec) {

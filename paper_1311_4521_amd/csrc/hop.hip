@@ -67,43 +67,6 @@ constexpr int kLinkAux = TMH_HOP_NT_LINKS ? 2 : 0;
 template <typename R> constexpr int out_aux() { return (TMH_HOP_NT_STORE && sizeof(R) == 8) ? 2 : 0; }
 constexpr int kHopBlock = TMH_HOP_BLOCK;
 
-// e_mu applied to the lower spin pair (p2, p3) of the chiral basis:
-// e_0 = -1, e_1 = -i sigma_1, e_2 = -i sigma_2, e_3 = -i sigma_3.
-template <typename R, int MU>
-__device__ __forceinline__ void e_lower(cx<R> p2, cx<R> p3, cx<R>& r0, cx<R>& r1) {
-    if constexpr (MU == 0) {
-        r0 = mk<R>(-p2.re, -p2.im);
-        r1 = mk<R>(-p3.re, -p3.im);
-    } else if constexpr (MU == 1) {
-        r0 = mk<R>(p3.im, -p3.re);  // -i p3
-        r1 = mk<R>(p2.im, -p2.re);  // -i p2
-    } else if constexpr (MU == 2) {
-        r0 = mk<R>(-p3.re, -p3.im);
-        r1 = p2;
-    } else {
-        r0 = mk<R>(p2.im, -p2.re);  // -i p2
-        r1 = mul_i(p3);             //  i p3
-    }
-}
-
-// e_mu^dagger applied to (g0, g1).
-template <typename R, int MU>
-__device__ __forceinline__ void edag(cx<R> g0, cx<R> g1, cx<R>& r0, cx<R>& r1) {
-    if constexpr (MU == 0) {
-        r0 = mk<R>(-g0.re, -g0.im);
-        r1 = mk<R>(-g1.re, -g1.im);
-    } else if constexpr (MU == 1) {
-        r0 = mul_i(g1);
-        r1 = mul_i(g0);
-    } else if constexpr (MU == 2) {
-        r0 = g1;
-        r1 = mk<R>(-g0.re, -g0.im);
-    } else {
-        r0 = mul_i(g0);
-        r1 = mk<R>(g1.im, -g1.re);  // -i g1
-    }
-}
-
 // Data one of the 8 terms needs: the neighbour's spinor and the link.
 template <typename R> struct TermData {
     cx<R> psi[4][3];

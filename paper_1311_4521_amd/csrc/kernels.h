@@ -23,6 +23,22 @@ template <typename R> struct HopArgs {
     R d_re[2], d_im[2];               // coefficient of aux, upper/lower spins
 };
 
+// Gauge-link derivative of Re <X, H Y> (force.hip): FP64 fields, the force
+// in the internal gauge layout, force += coeff * (TA(M) | Euclidean gradient).
+struct ForceArgs {
+    double2* force;
+    const double2* gauge;
+    const double2* X;      // on the output parity of H
+    const double2* Y;      // on the input parity of H
+    Geo g;
+    int pout;              // output parity of H
+    int kind;              // 0: su(3) force TA(M), 1: Euclidean gradient
+    double kappa, coeff;
+    double ph_re[4], ph_im[4];
+    double cx_re[2], cx_im[2];  // X_eff = c_{s/2} X_s
+};
+hipError_t launch_force(const ForceArgs& a, hipStream_t s);
+
 int hop_blocks(const Geo& g);
 template <typename R> hipError_t launch_hop(const HopArgs<R>& a, int mode, hipStream_t s);
 
@@ -33,6 +49,8 @@ template <typename R>
 hipError_t launch_spinor_import(typename Word<R>::T* dst, const double* src, const Geo& g, hipStream_t s);
 template <typename R>
 hipError_t launch_spinor_export(double* dst, const typename Word<R>::T* src, const Geo& g, hipStream_t s);
+template <typename R>
+hipError_t launch_gauge_export(double* dst, const typename Word<R>::T* src, const Geo& g, hipStream_t s);
 // Internal FP64 -> FP32 (spinor: ncomp = 12, gauge: ncomp = 72), and FP32 -> FP64.
 hipError_t launch_narrow(float2* dst, const double2* src, int ncomp, const Geo& g, hipStream_t s);
 hipError_t launch_widen(double2* dst, const float2* src, int ncomp, const Geo& g, hipStream_t s);

@@ -46,6 +46,31 @@ __global__ void __launch_bounds__(kBlock) gauge_import_kernel(typename Word<R>::
 }
 
 template <typename R>
+__global__ void __launch_bounds__(kBlock) gauge_export_kernel(double2* __restrict__ dst,
+                                                              const typename Word<R>::T* __restrict__ src, Geo g,
+                                                              int64_t V) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= 4 * V) return;
+    const int mu = (int)(t / V);
+    const int64_t lex = t - (int64_t)mu * V;
+    int64_t r = lex;
+    const int z = (int)(r % g.L[3]);
+    r /= g.L[3];
+    const int y = (int)(r % g.L[2]);
+    r /= g.L[2];
+    const int x = (int)(r % g.L[1]);
+    const int tt = (int)(r / g.L[1]);
+    const int p = (tt + x + y + z) & 1;
+    const int i = (int)(lex >> 1);
+    double2* d = dst + t * 9;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const typename Word<R>::T v = src[((int64_t)(p * 4 + mu) * 9 + k) * g.S + i];
+        d[k] = make_double2((double)v.x, (double)v.y);
+    }
+}
+
+template <typename R>
 __global__ void __launch_bounds__(kBlock) spinor_import_kernel(typename Word<R>::T* __restrict__ dst,
                                                                const double2* __restrict__ src, Geo g) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -104,6 +129,15 @@ hipError_t launch_gauge_import(typename Word<R>::T* dst, const double* src, cons
 }
 
 template <typename R>
+hipError_t launch_gauge_export(double* dst, const typename Word<R>::T* src, const Geo& g, hipStream_t s) {
+    const int64_t V = 2 * (int64_t)g.Vh;
+    if (V == 0) return hipSuccess;
+    hipLaunchKernelGGL((gauge_export_kernel<R>), dim3(nblocks(4 * V)), dim3(kBlock), 0, s, (double2*)dst, src,
+                       g, V);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_spinor_import(typename Word<R>::T* dst, const double* src, const Geo& g, hipStream_t s) {
     if (g.Vh == 0) return hipSuccess;
     hipLaunchKernelGGL((spinor_import_kernel<R>), dim3(nblocks(g.Vh)), dim3(kBlock), 0, s, dst,
@@ -133,6 +167,8 @@ hipError_t launch_widen(double2* dst, const float2* src, int ncomp, const Geo& g
 
 template hipError_t launch_gauge_import<double>(double2*, const double*, const Geo&, hipStream_t);
 template hipError_t launch_gauge_import<float>(float2*, const double*, const Geo&, hipStream_t);
+template hipError_t launch_gauge_export<double>(double*, const double2*, const Geo&, hipStream_t);
+template hipError_t launch_gauge_export<float>(double*, const float2*, const Geo&, hipStream_t);
 template hipError_t launch_spinor_import<double>(double2*, const double*, const Geo&, hipStream_t);
 template hipError_t launch_spinor_import<float>(float2*, const double*, const Geo&, hipStream_t);
 template hipError_t launch_spinor_export<double>(double*, const double2*, const Geo&, hipStream_t);

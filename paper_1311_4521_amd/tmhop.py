@@ -73,7 +73,9 @@ _sig("tmh_hop_apply", _I, [_P, _I, _P, _P, _P, _D, _P, _I])
 _sig("tmh_qtm_apply", _I, [_P, _P, _P, _P, _D, _D, _P, _I, _I])
 _sig("tmh_cg_solve", _I, [_P, _P, _P, _P, _D, _D, _P, _D, _I, _I, ctypes.POINTER(_I),
                           ctypes.POINTER(_D)])
-_sig("tmh_hop_force", _I, [_P, _I, _P, _P, _P, _P, _D, _P, _D])
+_sig("tmh_hop_force", _I, [_P, _I, _P, _P, _P, _P, _D, _P, _D, _I])
+_sig("tmh_qtm_force", _I, [_P, _P, _P, _P, _P, _D, _D, _P, _I, _D, _I])
+_sig("tmh_gauge_export", _I, [_P, _P, _P, _I])
 _sig("tmh_scalar_prod_r", _I, [_P, ctypes.POINTER(_D), _P, _P, _I])
 _sig("tmh_norm2", _I, [_P, ctypes.POINTER(_D), _P, _I])
 _sig("tmh_stream_copy", _I, [_P, _P, _P, _S])
@@ -84,7 +86,8 @@ _sig("tmh_status_string", ctypes.c_char_p, [_I])
 EXPORTED = ("tmh_lattice_create", "tmh_lattice_destroy", "tmh_lattice_set_stream",
             "tmh_half_volume", "tmh_site_stride", "tmh_spinor_bytes", "tmh_gauge_bytes",
             "tmh_gauge_import", "tmh_spinor_import", "tmh_spinor_export", "tmh_hop_apply",
-            "tmh_qtm_apply", "tmh_cg_solve", "tmh_hop_force", "tmh_scalar_prod_r", "tmh_norm2",
+            "tmh_qtm_apply", "tmh_cg_solve", "tmh_hop_force", "tmh_qtm_force", "tmh_gauge_export",
+            "tmh_scalar_prod_r", "tmh_norm2",
             "tmh_stream_copy", "tmh_profile_enable", "tmh_profile_read", "tmh_status_string")
 
 
@@ -168,9 +171,10 @@ class Lattice:
         f = torch.zeros if zero else torch.empty
         return f((12, self.S, 2), dtype=_DTYPE[p], device=self.device)
 
-    def new_gauge(self, prec=F64):
+    def new_gauge(self, prec=F64, zero=False):
         p = _PRECS[prec]
-        return torch.empty((2, 4, 9, self.S, 2), dtype=_DTYPE[p], device=self.device)
+        f = torch.zeros if zero else torch.empty
+        return f((2, 4, 9, self.S, 2), dtype=_DTYPE[p], device=self.device)
 
 
 def _complex_dev(x, shape, device):
@@ -276,11 +280,49 @@ def cg_solve(lat: Lattice, x, b, gauge, kappa, mu, theta, rel_tol=1e-10, max_ite
     return it.value, res.value, st == TMH_OK
 
 
-def hop_force(lat: Lattice, direction, force, gauge, left, right, kappa, theta, coeff):
+FORCE_SU3, FORCE_EUCLID = 0, 1
+_KINDS = {"su3": FORCE_SU3, "euclid": FORCE_EUCLID, FORCE_SU3: FORCE_SU3, FORCE_EUCLID: FORCE_EUCLID}
+
+
+def hop_force(lat: Lattice, direction, force, gauge, left, right, kappa, theta, coeff=1.0,
+              kind="su3"):
+    """force += coeff * dRe<left, H right>/dU (FP64 internal layouts; kind
+    'su3' = TA(M), 'euclid' = gradient for U a free complex matrix)."""
+    _expect(force, lat, F64, "gauge")
+    _expect(gauge, lat, F64, "gauge")
+    _expect(left, lat, F64, "spinor")
+    _expect(right, lat, F64, "spinor")
     th, _keep = _theta(theta)
     lat._sync_stream()
-    _check(_lib.tmh_hop_force(lat.handle, _DIRS[direction], _ptr(force), _ptr(gauge), _ptr(left),
-                              _ptr(right), float(kappa), th, float(coeff)), "tmh_hop_force")
+    _check(_lib.tmh_hop_force(lat.handle, _DIRS[direction], force.data_ptr(), gauge.data_ptr(),
+                              left.data_ptr(), right.data_ptr(), float(kappa), th, float(coeff),
+                              _KINDS[kind]), "tmh_hop_force")
+    return force
+
+
+def qtm_force(lat: Lattice, force, gauge, chi, psi, kappa, mu, theta, sign=+1, coeff=1.0,
+              kind="su3"):
+    """force += coeff * dRe<chi, Qhat(sign) psi>/dU (FP64 internal layouts)."""
+    _expect(force, lat, F64, "gauge")
+    _expect(gauge, lat, F64, "gauge")
+    _expect(chi, lat, F64, "spinor")
+    _expect(psi, lat, F64, "spinor")
+    th, _keep = _theta(theta)
+    lat._sync_stream()
+    _check(_lib.tmh_qtm_force(lat.handle, force.data_ptr(), gauge.data_ptr(), chi.data_ptr(),
+                              psi.data_ptr(), float(kappa), float(mu), th, int(sign), float(coeff),
+                              _KINDS[kind]), "tmh_qtm_force")
+    return force
+
+
+def gauge_export(lat: Lattice, src, prec=F64):
+    """Internal gauge-layout field -> canonical complex128 [4][V][3][3] on the device."""
+    p = _PRECS[prec]
+    _expect(src, lat, p, "gauge")
+    out = torch.empty((4, 2 * lat.Vh, 3, 3), dtype=torch.complex128, device=lat.device)
+    lat._sync_stream()
+    _check(_lib.tmh_gauge_export(lat.handle, out.data_ptr(), src.data_ptr(), p), "tmh_gauge_export")
+    return out
 
 
 def scalar_prod_r(lat: Lattice, a, b, prec=F64) -> float:

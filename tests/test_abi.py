@@ -56,5 +56,6 @@ def test_null_handle_rejected():
     from paper_1311_4521_amd import tmhop
     lib = tmhop._lib
     assert lib.tmh_hop_apply(None, 0, None, None, None, 0.1, None, 0) == tmhop.TMH_ERR_ARG
-    assert lib.tmh_hop_force(None, 0, None, None, None, None, 0.1, None, 1.0) == tmhop.TMH_ERR_ARG
+    assert lib.tmh_hop_force(None, 0, None, None, None, None, 0.1, None, 1.0, 0) == tmhop.TMH_ERR_ARG
+    assert lib.tmh_qtm_force(None, None, None, None, None, 0.1, 0.1, None, 1, 1.0, 0) == tmhop.TMH_ERR_ARG
     assert lib.tmh_spinor_bytes(None, 0) == 0

@@ -1,0 +1,168 @@
+"""Gauge-link derivative and autograd on the GPU, against the oracle and
+against central finite differences taken on the GPU.
+
+Bar: per-link relative error <= 1e-13 against the oracle (FP64), and
+agreement 1e-6 with central differences of step 1e-6 (the difference of the
+two operator applications is formed site-wise, so sites the link cannot
+reach cancel exactly)."""
+
+import numpy as np
+import pytest
+import torch
+
+import fieldgen
+import oracle
+import paper_1311_4521_amd as tm
+from paper_1311_4521_amd import autograd as tag
+from helpers import THETA_AP, gauss, haar, mu_of
+
+pytestmark = pytest.mark.gpu
+
+TWIST = (0.5, 0.25, -0.3, 0.7)
+GEN = 1j * fieldgen.gell_mann() / 2
+
+
+def link_rel_err(got, ref):
+    got = np.asarray(got).reshape(-1, 9)
+    ref = np.asarray(ref).reshape(-1, 9)
+    num = np.linalg.norm(got - ref, axis=1)
+    den = np.linalg.norm(ref, axis=1)
+    den = np.maximum(den, 1e-6 * np.sqrt(np.mean(den ** 2)))
+    return float(np.max(num / den))
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", ["su3", "euclid"])
+@pytest.mark.parametrize("direction", ["eo", "oe"])
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (6, 2, 4, 2), (4, 6, 2, 6), (6, 8, 10, 4)],
+                         ids=lambda d: "x".join(map(str, d)))
+def test_hop_force_matches_oracle(dims, direction, kind):
+    kappa, coeff = 0.137, -0.7
+    U = haar(dims, 301)
+    Vh = int(np.prod(dims)) // 2
+    X, Y = gauss(Vh, 302), gauss(Vh, 303)
+    F0 = fieldgen.gauge_haar(dims, 304)     # something to accumulate onto
+    lat = tm.Lattice(dims)
+    G = tm.gauge_import(lat, U)
+    F = tm.gauge_import(lat, F0)
+    tm.hop_force(lat, direction, F, G, tm.spinor_import(lat, X), tm.spinor_import(lat, Y), kappa,
+                 TWIST, coeff, kind)
+    got = host(tm.gauge_export(lat, F))
+    ref = oracle.hop_force(dims, direction, U, X, Y, kappa, TWIST, coeff, kind, out=F0)
+    assert link_rel_err(got - F0, ref - F0) <= 1e-13
+
+
+@pytest.mark.parametrize("kind", ["su3", "euclid"])
+@pytest.mark.parametrize("sign", [+1, -1])
+@pytest.mark.parametrize("dims", [(6, 8, 10, 4), (8, 8, 8, 8)], ids=lambda d: "x".join(map(str, d)))
+def test_qtm_force_matches_oracle(dims, sign, kind):
+    kappa, mu = 0.1632, 0.45
+    U = haar(dims, 311)
+    Vh = int(np.prod(dims)) // 2
+    chi, psi = gauss(Vh, 312), gauss(Vh, 313)
+    lat = tm.Lattice(dims)
+    G = tm.gauge_import(lat, U)
+    F = lat.new_gauge(zero=True)
+    tm.qtm_force(lat, F, G, tm.spinor_import(lat, chi), tm.spinor_import(lat, psi), kappa, mu,
+                 THETA_AP, sign, 1.0, kind)
+    ref = oracle.qtm_force(dims, U, chi, psi, kappa, mu, THETA_AP, sign, kind=kind)
+    assert link_rel_err(host(tm.gauge_export(lat, F)), ref) <= 1e-13
+
+
+def test_gauge_export_roundtrip():
+    dims = (4, 6, 2, 6)
+    U = haar(dims, 321)
+    lat = tm.Lattice(dims)
+    assert np.array_equal(host(tm.gauge_export(lat, tm.gauge_import(lat, U))), U)
+
+
+def expm_herm(A):
+    w, v = np.linalg.eigh(A)
+    return (v * np.exp(1j * w)) @ v.conj().T
+
+
+def set_link(G, dims, mu, lex, M):
+    """Writes the 3x3 matrix M as link U_mu(lex) into an internal FP64 gauge tensor."""
+    c = np.unravel_index(lex, dims)
+    p = int(sum(c)) % 2
+    t = torch.from_numpy(np.stack([M.real.ravel(), M.imag.ravel()], axis=1)).to(G.device)
+    G[p, mu, :, lex >> 1, :] = t
+
+
+@pytest.mark.slow
+def test_force_24x24x24x48_oracle_and_finite_differences():
+    """The adjoint workload: 24^3x48 Haar links, Gaussian chi and psi."""
+    dims, kappa, mt = (48, 24, 24, 24), 0.1632, 0.0013
+    mu = mu_of(kappa, mt)
+    seed = fieldgen.SEEDS["adjoint24"]
+    U = fieldgen.gauge_haar(dims, seed)
+    Vh = int(np.prod(dims)) // 2
+    chi, psi = gauss(Vh, 100 + seed), gauss(Vh, 200 + seed)
+    lat = tm.Lattice(dims)
+    G = tm.gauge_import(lat, U)
+    tc, tp = tm.spinor_import(lat, chi), tm.spinor_import(lat, psi)
+    F = lat.new_gauge(zero=True)
+    tm.qtm_force(lat, F, G, tc, tp, kappa, mu, THETA_AP, +1)
+    Fh = host(tm.gauge_export(lat, F))
+    ref = oracle.qtm_force(dims, U, chi, psi, kappa, mu, THETA_AP, +1)
+    assert link_rel_err(Fh, ref) <= 1e-13
+    # central differences on the GPU at sampled links (boundary and interior)
+    g = fieldgen.rng(331)
+    V = int(np.prod(dims))
+    links = [(0, 0), (0, V - 1), (3, V // 2 + 7)] + \
+        [(int(g.integers(0, 4)), int(g.integers(0, V))) for _ in range(9)]
+    qp, qm = lat.new_spinor(), lat.new_spinor()
+    h = 1e-6
+    for mu_, l in links:
+        fd = np.empty(8)
+        for a in range(8):
+            Gp = G.clone()
+            set_link(Gp, dims, mu_, l, expm_herm(h * fieldgen.gell_mann()[a] / 2) @ U[mu_, l])
+            tm.qtm_apply(lat, qp, Gp, tp, kappa, mu, THETA_AP, +1)
+            set_link(Gp, dims, mu_, l, expm_herm(-h * fieldgen.gell_mann()[a] / 2) @ U[mu_, l])
+            tm.qtm_apply(lat, qm, Gp, tp, kappa, mu, THETA_AP, +1)
+            fd[a] = tm.scalar_prod_r(lat, tc, qp - qm) / (2 * h)
+        an = np.array([np.trace(GEN[a] @ Fh[mu_, l]).real for a in range(8)])
+        assert np.linalg.norm(fd - an) / np.linalg.norm(an) < 1e-6, (mu_, l)
+
+
+def test_autograd_gradcheck_bilinear():
+    dims, kappa, mu = (2, 2, 2, 4), 0.16, 0.3
+    lat = tm.Lattice(dims)
+    U = torch.from_numpy(haar(dims, 341)).cuda().requires_grad_()
+    Vh = lat.Vh
+    psi = torch.from_numpy(gauss(Vh, 342)).cuda().requires_grad_()
+    chi = torch.from_numpy(gauss(Vh, 343)).cuda().requires_grad_()
+    f = lambda p, u, c: tag.QtmBilinear.apply(p, u, c, lat, kappa, mu, THETA_AP, +1)
+    assert torch.autograd.gradcheck(f, (psi, U, chi), eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_autograd_gradcheck_norm2():
+    dims, kappa, mu = (2, 2, 2, 4), 0.16, 0.3
+    lat = tm.Lattice(dims)
+    U = torch.from_numpy(haar(dims, 351)).cuda().requires_grad_()
+    psi = torch.from_numpy(gauss(lat.Vh, 352)).cuda().requires_grad_()
+    f = lambda p, u: tag.QtmNorm2.apply(p, u, lat, kappa, mu, THETA_AP, -1)
+    assert torch.autograd.gradcheck(f, (psi, U), eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_autograd_matches_oracle_gradients():
+    """psi-gradient = Qhat(-) chi and link gradient = oracle Euclidean force."""
+    dims, kappa, mu = (6, 8, 10, 4), 0.1632, 0.02
+    lat = tm.Lattice(dims)
+    Uh = haar(dims, 361)
+    chi_h, psi_h = gauss(lat.Vh, 362), gauss(lat.Vh, 363)
+    U = torch.from_numpy(Uh).cuda().requires_grad_()
+    psi = torch.from_numpy(psi_h).cuda().requires_grad_()
+    chi = torch.from_numpy(chi_h).cuda()
+    L = tag.qtm_bilinear(lat, chi, psi, U, kappa, mu, THETA_AP, +1)
+    L.backward()
+    ref_L = oracle.re_dot(chi_h, oracle.qtm(dims, Uh, psi_h, kappa, mu, THETA_AP, +1))
+    assert abs(L.item() - ref_L) <= 1e-12 * abs(ref_L)
+    gp = oracle.qtm(dims, Uh, chi_h, kappa, mu, THETA_AP, -1)
+    assert np.abs(host(psi.grad) - gp).max() <= 1e-12 * np.abs(gp).max()
+    gU = oracle.qtm_force(dims, Uh, chi_h, psi_h, kappa, mu, THETA_AP, +1, kind="euclid")
+    assert link_rel_err(host(U.grad), gU) <= 1e-12
