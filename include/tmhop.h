@@ -143,6 +143,20 @@ tmh_status tmh_cg_solve(tmh_lattice* lat, void* x, const void* b, const void* ga
                         double kappa, double mu, const double theta[4], double rel_tol,
                         int max_iter, tmh_prec inner, int* iters, double* true_rel_res);
 
+/* Full-lattice solve of M x = b, M = (1 + i mt gamma_5) - H the twisted-mass
+ * Wilson operator on both checkerboards (what the inverter of the
+ * introduction solves), through the even-odd split:
+ *   bhat_o = b_o + H_oe A^-1 b_e,  Qhat(+)^+ Qhat(+) x_o = Qhat(-) gamma_5 bhat_o
+ *   (tmh_cg_solve's system, x_odd holding the initial guess),
+ *   x_e = A^-1 (b_e + H_eo x_o).
+ * All buffers FP64 internal layout; x_even, x_odd must not overlap the inputs
+ * or each other.  rel_tol, max_iter, inner, *iters and *true_rel_res are those
+ * of the odd CG (its normal-equation residual).  Blocks. */
+tmh_status tmh_solve_full(tmh_lattice* lat, void* x_even, void* x_odd, const void* b_even,
+                          const void* b_odd, const void* gauge, double kappa, double mu,
+                          const double theta[4], double rel_tol, int max_iter, tmh_prec inner,
+                          int* iters, double* true_rel_res);
+
 /* Gauge-link derivative, the paper's "fermionic derivative" (Section 2,
  * "Race conditions and Memory Locking", which updates it with atomics; here
  * every link has one writer).  For L = Re <left, H right> with H = H_eo

@@ -55,11 +55,12 @@ def lib():
         L.orc_re_dot.restype = D
         L.orc_hop_force.argtypes = [P, I, P, P, P, P, D, P, D, I]
         L.orc_qtm_force.argtypes = [P, P, P, P, P, D, D, P, I, D, I]
+        L.orc_full_operator.argtypes = [P, P, P, P, D, D, P, I]
         L.orc_gamma.argtypes = [I, P]
         L.orc_gamma.restype = None
         L.orc_num_threads.restype = I
         for name in ("orc_hop", "orc_hop_sites", "orc_hop_full", "orc_eo_sites", "orc_qtm",
-                     "orc_cg", "orc_hop_force", "orc_qtm_force"):
+                     "orc_cg", "orc_hop_force", "orc_qtm_force", "orc_full_operator"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -149,6 +150,17 @@ def qtm(dims, gauge, psi, kappa, mu, theta, sign=+1):
     out = np.empty_like(psi)
     _check(lib().orc_qtm(_p(_dims(dims)), _p(out), _p(gauge), _p(psi), float(kappa), float(mu),
                          _p(_theta(theta)), int(sign)), "qtm")
+    return out
+
+
+def full_operator(dims, gauge, psi, kappa, mu, theta, sign=+1):
+    """M psi = (1 + i sign 2 kappa mu gamma_5) psi - H psi on a lex-ordered
+    full-lattice spinor [V][4][3]."""
+    gauge = _c128(gauge)
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    _check(lib().orc_full_operator(_p(_dims(dims)), _p(out), _p(gauge), _p(psi), float(kappa),
+                                   float(mu), _p(_theta(theta)), int(sign)), "full_operator")
     return out
 
 

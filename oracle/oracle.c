@@ -346,6 +346,29 @@ int orc_qtm(const int dims[4], double* out, const double* gauge, const double* i
     return st;
 }
 
+/* Full-lattice twisted-mass Wilson operator on lex-ordered spinors [V][4][3]:
+ * out = (1 + i sign mt gamma_5) in - H in, the matrix whose even-odd Schur
+ * complement is Mhat. */
+int orc_full_operator(const int dims[4], double* out, const double* gauge, const double* in,
+                      double kappa, double mu, const double theta[4], int sign)
+{
+    if (sign != 1 && sign != -1) return -1;
+    geom g;
+    int st = geom_init(&g, dims);
+    if (st) return st;
+    const int64_t V = g.V;
+    geom_free(&g);
+    cplx* h = malloc(sizeof(cplx) * 12 * V);
+    if (!h) return -2;
+    st = orc_hop_full(dims, (double*)h, gauge, in, kappa, theta);
+    if (!st) {
+        spin_lincomb_g5((cplx*)out, (const cplx*)in, V, 1.0, I * (2.0 * kappa * mu * sign));
+        for (int64_t k = 0; k < 12 * V; ++k) ((cplx*)out)[k] -= h[k];
+    }
+    free(h);
+    return st;
+}
+
 /* ----------------------------------------------------------- linear algebra */
 
 /* Re <a, b> = Re sum conj(a_k) b_k, Kahan-compensated, serial. */

@@ -6,9 +6,9 @@ in ``include/tmhop.h``); ``tmhop`` is its ctypes binding.
 
 from .tmhop import (EO, F32, F64, OE, Lattice, TmhError, cg_solve, gauge_export, gauge_import,
                     hop_apply, hop_force, lattice_create, norm2, qtm_apply, qtm_force,
-                    scalar_prod_r, spinor_export, spinor_import, status_string)
+                    scalar_prod_r, solve_full, spinor_export, spinor_import, status_string)
 
 __all__ = ["EO", "OE", "F64", "F32", "Lattice", "TmhError", "lattice_create", "gauge_import",
            "spinor_import", "spinor_export", "gauge_export", "hop_apply", "qtm_apply", "cg_solve",
-           "hop_force", "qtm_force",
+           "hop_force", "qtm_force", "solve_full",
            "scalar_prod_r", "norm2", "status_string"]

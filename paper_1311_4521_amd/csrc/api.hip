@@ -27,7 +27,8 @@ struct tmh_lattice {
     double* h_scal;         // pinned host mirror of scal
     int* h_flags;           // pinned host mirror of flags
     void* even[2];          // intermediate even field per precision (Qtm)
-    void* even2;            // second FP64 even field (force chain)
+    void* even2;            // second FP64 even field (force chain, full solve)
+    void* odd_rhs[2];       // FP64 odd fields of the full-lattice solve
     double2* v64[4];        // FP64 CG vectors r, p, v, q
     float2* v32[5];         // FP32 inner CG vectors r, p, v, q, d
     float2* gauge32;        // FP32 copy of the links for the mixed-precision inner solve
@@ -443,6 +444,7 @@ void tmh_lattice_destroy(tmh_lattice* l) {
     if (l->h_flags) (void)hipHostFree(l->h_flags);
     for (void* p : l->even) (void)hipFree(p);
     (void)hipFree(l->even2);
+    for (void* p : l->odd_rhs) (void)hipFree(p);
     for (void* p : l->v64) (void)hipFree(p);
     for (void* p : l->v32) (void)hipFree(p);
     (void)hipFree(l->gauge32);
@@ -613,6 +615,64 @@ tmh_status tmh_qtm_force(tmh_lattice* l, void* force, const void* gauge, const v
     TMH_TRY_HIP(force_launch(l, 0, force, gauge, l->even2, psi, kappa, theta, -coeff, kind, 1.0 / D, mt / D,
                              -1.0 / D, mt / D));
     return TMH_OK;
+}
+
+tmh_status tmh_solve_full(tmh_lattice* l, void* x_even, void* x_odd, const void* b_even, const void* b_odd,
+                          const void* gauge, double kappa, double mu, const double theta[4], double rel_tol,
+                          int max_iter, tmh_prec inner, int* iters, double* true_rel_res) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(inner));
+    TMH_TRY(check_theta(theta));
+    if (!x_even || !x_odd || !b_even || !b_odd || !gauge || !iters || !true_rel_res) return TMH_ERR_ARG;
+    if (!isfinite(kappa) || !isfinite(mu) || !(rel_tol > 0.0) || max_iter < 0) return TMH_ERR_ARG;
+    const size_t sb = spinor_bytes(l, TMH_F64), gb = gauge_bytes(l, TMH_F64);
+    const void* ins[3] = {b_even, b_odd, gauge};
+    const size_t insz[3] = {sb, sb, gb};
+    for (int k = 0; k < 3; ++k)
+        if (overlap(x_even, sb, ins[k], insz[k]) || overlap(x_odd, sb, ins[k], insz[k])) return TMH_ERR_ALIAS;
+    if (overlap(x_even, sb, x_odd, sb)) return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    TMH_TRY(ensure(&l->even2, sb));
+    for (int k = 0; k < 2; ++k) TMH_TRY(ensure(&l->odd_rhs[k], sb));
+    const double mt = 2.0 * kappa * mu;
+    const double D = 1.0 + mt * mt;
+    // A^-1 = (1 - i mt gamma_5)/D: upper (1 - i mt)/D, lower (1 + i mt)/D
+    const double ai_re = 1.0 / D, ai_up = -mt / D, ai_dn = mt / D;
+    // even2 = A^-1 b_e
+    TMH_TRY_HIP(tmh::launch_chiral_scale((double2*)l->even2, (const double2*)b_even, ai_re, ai_up, ai_re, ai_dn,
+                                         l->g, l->stream));
+    // odd_rhs[0] = gamma_5 (b_o + H_oe A^-1 b_e)
+    HopArgs<double> a = hop_args<double>(l, 1, l->odd_rhs[0], gauge, l->even2, theta);
+    a.aux = (const double2*)b_odd;
+    a.c_re[0] = kappa;
+    a.c_re[1] = -kappa;
+    a.d_re[0] = 1.0;
+    a.d_re[1] = -1.0;
+    TMH_TRY_HIP(hop_launch<double>(l, a, 1));
+    // odd_rhs[1] = Qhat(-) gamma_5 bhat_o: the right-hand side of Qhat^+ Qhat x_o
+    void* te;
+    TMH_TRY(even_scratch(l, TMH_F64, &te));
+    TMH_TRY(qtm_launch<double>(l, l->odd_rhs[1], gauge, l->odd_rhs[0], te, kappa, mu, theta, -1, nullptr,
+                               nullptr));
+    tmh_status st = inner == TMH_F64 ? cg_fp64(l, x_odd, l->odd_rhs[1], gauge, kappa, mu, theta, rel_tol, max_iter,
+                                               iters, true_rel_res)
+                                     : cg_mixed(l, x_odd, l->odd_rhs[1], gauge, kappa, mu, theta, rel_tol,
+                                                max_iter, iters, true_rel_res);
+    if (st != TMH_OK && st != TMH_ERR_NOT_CONVERGED) return st;
+    // x_e = A^-1 (b_e + H_eo x_o)
+    HopArgs<double> b = hop_args<double>(l, 0, x_even, gauge, x_odd, theta);
+    b.aux = (const double2*)b_even;
+    b.c_re[0] = kappa * ai_re;
+    b.c_im[0] = kappa * ai_up;
+    b.c_re[1] = kappa * ai_re;
+    b.c_im[1] = kappa * ai_dn;
+    b.d_re[0] = ai_re;
+    b.d_im[0] = ai_up;
+    b.d_re[1] = ai_re;
+    b.d_im[1] = ai_dn;
+    TMH_TRY_HIP(hop_launch<double>(l, b, 1));
+    if (hipStreamSynchronize(l->stream) != hipSuccess) return TMH_ERR_HIP;
+    return st;
 }
 
 tmh_status tmh_gauge_export(tmh_lattice* l, double* dst, const void* src, tmh_prec prec) {

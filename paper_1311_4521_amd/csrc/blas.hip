@@ -175,6 +175,22 @@ __global__ void __launch_bounds__(kBlock) add_widen_kernel(double2* __restrict__
     }
 }
 
+// out_s = c_{s/2} in_s: a site-local function of gamma_5 (upper spins take
+// c_up, lower spins c_dn), e.g. (1 +- i mt gamma_5)^-1.
+__global__ void __launch_bounds__(kBlock) chiral_scale_kernel(double2* __restrict__ out,
+                                                              const double2* __restrict__ in, double cu_re,
+                                                              double cu_im, double cd_re, double cd_im, Geo g) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < g.Vh; i += gridDim.x * kBlock) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const int64_t k = (int64_t)c * g.S + i;
+            const double2 v = in[k];
+            const double a = c < 6 ? cu_re : cd_re, b = c < 6 ? cu_im : cd_im;
+            out[k] = make_double2(a * v.x - b * v.y, a * v.y + b * v.x);
+        }
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kBlock) copy_kernel(typename Word<R>::T* __restrict__ dst,
                                                       const typename Word<R>::T* __restrict__ src, Geo g) {
@@ -279,6 +295,13 @@ template <typename R>
 hipError_t launch_sub_norm(typename Word<R>::T* out, const typename Word<R>::T* a, const typename Word<R>::T* b,
                            double* partial, const Geo& g, hipStream_t s) {
     hipLaunchKernelGGL((sub_norm_kernel<R>), dim3(blas_blocks(g)), dim3(kBlock), 0, s, out, a, b, partial, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_chiral_scale(double2* out, const double2* in, double cu_re, double cu_im, double cd_re,
+                               double cd_im, const Geo& g, hipStream_t s) {
+    hipLaunchKernelGGL(chiral_scale_kernel, dim3(blas_blocks(g)), dim3(kBlock), 0, s, out, in, cu_re, cu_im, cd_re,
+                       cd_im, g);
     return hipGetLastError();
 }
 

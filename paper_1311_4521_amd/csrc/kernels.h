@@ -81,6 +81,9 @@ hipError_t launch_cg_p(typename Word<R>::T* p, const typename Word<R>::T* r, con
 template <typename R>
 hipError_t launch_sub_norm(typename Word<R>::T* out, const typename Word<R>::T* a,
                            const typename Word<R>::T* b, double* partial, const Geo& g, hipStream_t s);
+// out_s = c_up in_s (spins 0,1) or c_dn in_s (spins 2,3), FP64.
+hipError_t launch_chiral_scale(double2* out, const double2* in, double cu_re, double cu_im, double cd_re,
+                               double cd_im, const Geo& g, hipStream_t s);
 // x += y (FP64 x, FP32 y): defect-correction update.
 hipError_t launch_add_widen(double2* x, const float2* y, const Geo& g, hipStream_t s);
 template <typename R>

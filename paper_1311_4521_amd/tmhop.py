@@ -76,6 +76,8 @@ _sig("tmh_cg_solve", _I, [_P, _P, _P, _P, _D, _D, _P, _D, _I, _I, ctypes.POINTER
 _sig("tmh_hop_force", _I, [_P, _I, _P, _P, _P, _P, _D, _P, _D, _I])
 _sig("tmh_qtm_force", _I, [_P, _P, _P, _P, _P, _D, _D, _P, _I, _D, _I])
 _sig("tmh_gauge_export", _I, [_P, _P, _P, _I])
+_sig("tmh_solve_full", _I, [_P, _P, _P, _P, _P, _P, _D, _D, _P, _D, _I, _I, ctypes.POINTER(_I),
+                            ctypes.POINTER(_D)])
 _sig("tmh_scalar_prod_r", _I, [_P, ctypes.POINTER(_D), _P, _P, _I])
 _sig("tmh_norm2", _I, [_P, ctypes.POINTER(_D), _P, _I])
 _sig("tmh_stream_copy", _I, [_P, _P, _P, _S])
@@ -86,7 +88,7 @@ _sig("tmh_status_string", ctypes.c_char_p, [_I])
 EXPORTED = ("tmh_lattice_create", "tmh_lattice_destroy", "tmh_lattice_set_stream",
             "tmh_half_volume", "tmh_site_stride", "tmh_spinor_bytes", "tmh_gauge_bytes",
             "tmh_gauge_import", "tmh_spinor_import", "tmh_spinor_export", "tmh_hop_apply",
-            "tmh_qtm_apply", "tmh_cg_solve", "tmh_hop_force", "tmh_qtm_force", "tmh_gauge_export",
+            "tmh_qtm_apply", "tmh_cg_solve", "tmh_hop_force", "tmh_qtm_force", "tmh_gauge_export", "tmh_solve_full",
             "tmh_scalar_prod_r", "tmh_norm2",
             "tmh_stream_copy", "tmh_profile_enable", "tmh_profile_read", "tmh_status_string")
 
@@ -277,6 +279,27 @@ def cg_solve(lat: Lattice, x, b, gauge, kappa, mu, theta, rel_tol=1e-10, max_ite
                            ctypes.byref(it), ctypes.byref(res))
     if st not in (TMH_OK, TMH_ERR_NOT_CONVERGED):
         raise TmhError(st, "tmh_cg_solve")
+    return it.value, res.value, st == TMH_OK
+
+
+def solve_full(lat: Lattice, x_even, x_odd, b_even, b_odd, gauge, kappa, mu, theta, rel_tol=1e-10,
+               max_iter=10000, inner=F64):
+    """Full-lattice M x = b through the even-odd split (FP64 fields; x_odd
+    holds the initial guess of the odd CG).  Returns (iterations, odd
+    normal-equation true relative residual, converged)."""
+    for t, k in ((x_even, "spinor"), (x_odd, "spinor"), (b_even, "spinor"), (b_odd, "spinor"),
+                 (gauge, "gauge")):
+        _expect(t, lat, F64, k)
+    th, _keep = _theta(theta)
+    it = ctypes.c_int(0)
+    res = ctypes.c_double(0.0)
+    lat._sync_stream()
+    st = _lib.tmh_solve_full(lat.handle, x_even.data_ptr(), x_odd.data_ptr(), b_even.data_ptr(),
+                             b_odd.data_ptr(), gauge.data_ptr(), float(kappa), float(mu), th,
+                             float(rel_tol), int(max_iter), _PRECS[inner], ctypes.byref(it),
+                             ctypes.byref(res))
+    if st not in (TMH_OK, TMH_ERR_NOT_CONVERGED):
+        raise TmhError(st, "tmh_solve_full")
     return it.value, res.value, st == TMH_OK
 
 

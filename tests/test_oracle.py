@@ -233,6 +233,17 @@ def test_qtm_matches_dense_schur(dims):
     assert abs(s_full - s_ee * s_h) < 1e-10
 
 
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (6, 2, 4, 2)])
+def test_full_operator_matches_dense(dims):
+    theta, kappa, mu = (1.0, 0.0, 0.5, 0.0), 0.16, 0.37
+    U = fieldgen.gauge_haar(dims, 75)
+    psi = fieldgen.spinor_gauss(int(np.prod(dims)), 76)
+    for sign in (+1, -1):
+        M = dense.full_operator(dims, U, kappa, mu, theta, sign)
+        out = oracle.full_operator(dims, U, psi, kappa, mu, theta, sign)
+        assert rel(out.ravel(), M @ psi.ravel()) < 1e-14
+
+
 def test_cg_matches_dense_solve():
     dims, theta, kappa, mu = (2, 2, 2, 2), (1.0, 0, 0, 0), 0.1632, 0.0013 / (2 * 0.1632)
     U = fieldgen.gauge_haar(dims, 81)
