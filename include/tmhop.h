@@ -143,6 +143,49 @@ tmh_status tmh_cg_solve(tmh_lattice* lat, void* x, const void* b, const void* ga
                         double kappa, double mu, const double theta[4], double rel_tol,
                         int max_iter, tmh_prec inner, int* iters, double* true_rel_res);
 
+/* ------------------------------------------------------------------ batches
+ * Several right-hand sides on one lattice share each link load; several
+ * lattices share each launch.  A batch member is one lattice with nrhs
+ * FP64 fields stored back to back (field r at base + r * tmh_spinor_bytes).
+ * Tile shapes (sites x right-hand sides per workgroup): 0 = 256x1, 1 = 128x2,
+ * 2 = 64x4, 3 = 128x4, 4 = 64x12; -1 picks the autotuned shape of the handle
+ * (tmh_autotune_mrhs) or a default. */
+typedef struct {
+    tmh_lattice* lat;      /* every member on the same device, distinct handles */
+    int nrhs;              /* right-hand sides (>= 1) */
+    void* x;               /* in: initial guesses, out: solutions (odd, FP64) */
+    const void* b;         /* sources (odd, FP64) */
+    const void* gauge;     /* FP64 internal links of this lattice */
+    double kappa, mu;
+    double theta[4];
+} tmh_batch_member;
+
+/* out_r = H in_r for r < nrhs (in/out: nrhs fields of precision prec back to
+ * back), all in one launch; kappa folded in.  Enqueued on the stream. */
+tmh_status tmh_hop_apply_mrhs(tmh_lattice* lat, tmh_dir dir, void* out, const void* gauge,
+                              const void* in, int nrhs, double kappa, const double theta[4],
+                              tmh_prec prec, int shape);
+
+/* CG on Qhat(+)^dagger Qhat(+) for every (member, rhs) system at once (at most
+ * 8 members): one launch per operator step for the whole batch, per-system
+ * scalars and stopping flags on the device, and, with use_graph != 0, the 8
+ * launches of an iteration captured once into a HIP graph and replayed.
+ * Stopping rule, restarts and true residual as tmh_cg_solve, per system.
+ * iters[] and true_rel_res[] get one entry per system, members in order.
+ * Runs on a private stream ordered after the first member's stream; blocks.
+ * TMH_ERR_NOT_CONVERGED if any system missed rel_tol. */
+tmh_status tmh_batch_cg_solve(const tmh_batch_member* members, int nmembers, double rel_tol,
+                              int max_iter, int shape, int use_graph, int* iters,
+                              double* true_rel_res);
+
+/* Autotuner of the batch tile shape: times the multi-RHS hop of every shape on
+ * this lattice for nrhs (<= 16) right-hand sides and keeps the fastest in the
+ * handle (used by shape = -1).  With cache_path, a line
+ * "<arch> <T>x<LX>x<LY>x<LZ> <f64|f32> <nrhs> <shape> <us>" is looked up first
+ * and appended after timing.  Blocks. */
+tmh_status tmh_autotune_mrhs(tmh_lattice* lat, const void* gauge, int nrhs, tmh_prec prec,
+                             const char* cache_path, int* best_shape, double* best_us);
+
 /* Full-lattice solve of M x = b, M = (1 + i mt gamma_5) - H the twisted-mass
  * Wilson operator on both checkerboards (what the inverter of the
  * introduction solves), through the even-odd split:

@@ -1,11 +1,14 @@
 // C-ABI of libtmhop (declared in include/tmhop.h): lattice handle, argument
 // checks, the hopping-matrix and twisted-mass launchers, the CG drivers.
 #include <math.h>
+#include <stdio.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/tmhop.h"
@@ -29,6 +32,9 @@ struct tmh_lattice {
     void* even[2];          // intermediate even field per precision (Qtm)
     void* even2;            // second FP64 even field (force chain, full solve)
     void* odd_rhs[2];       // FP64 odd fields of the full-lattice solve
+    void* mrhs[5];          // multi-RHS CG fields r, p, v, q (odd) and the even te, FP64
+    int mrhs_cap;           // right-hand sides mrhs[] can hold
+    int tuned[2][17];       // autotuned batch tile shape per (precision, nrhs <= 16), -1: none
     double2* v64[4];        // FP64 CG vectors r, p, v, q
     float2* v32[5];         // FP32 inner CG vectors r, p, v, q, d
     float2* gauge32;        // FP32 copy of the links for the mixed-precision inner solve
@@ -414,6 +420,8 @@ tmh_status tmh_lattice_create(tmh_lattice** out, const int dims[4], int device, 
     for (int m = 0; m < 4; ++m) l->g.L[m] = dims[m];
     l->g.Vh = (int)(V / 2);
     l->g.S = (int)((V / 2 + 63) / 64 * 64);
+    for (auto& row : l->tuned)
+        for (int& v : row) v = -1;
     const int nh = tmh::hop_blocks(l->g), nbl = tmh::blas_blocks(l->g);
     l->npartial = nh > nbl ? nh : nbl;
     tmh_status st = ensure((void**)&l->partial, sizeof(double) * l->npartial);
@@ -445,6 +453,7 @@ void tmh_lattice_destroy(tmh_lattice* l) {
     for (void* p : l->even) (void)hipFree(p);
     (void)hipFree(l->even2);
     for (void* p : l->odd_rhs) (void)hipFree(p);
+    for (void* p : l->mrhs) (void)hipFree(p);
     for (void* p : l->v64) (void)hipFree(p);
     for (void* p : l->v32) (void)hipFree(p);
     (void)hipFree(l->gauge32);
@@ -673,6 +682,455 @@ tmh_status tmh_solve_full(tmh_lattice* l, void* x_even, void* x_odd, const void*
     TMH_TRY_HIP(hop_launch<double>(l, b, 1));
     if (hipStreamSynchronize(l->stream) != hipSuccess) return TMH_ERR_HIP;
     return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+namespace {
+
+int default_shape(const tmh_lattice* l, int nrhs, tmh_prec prec) {
+    if (nrhs >= 1 && nrhs <= 16 && l->tuned[prec][nrhs] >= 0) return l->tuned[prec][nrhs];
+    return nrhs >= 4 ? tmh::kShape1x4 : (nrhs >= 2 ? tmh::kShape2x2 : tmh::kShape4x1);
+}
+
+int hop_tiles(const Geo& g, int shape) {
+    int sw, ry;
+    tmh::batch_shape(shape, &sw, &ry);
+    return (g.Vh + 64 * sw - 1) / (64 * sw);
+}
+
+int hop_items(const Geo& g, int nrhs, int shape) {
+    int sw, ry;
+    tmh::batch_shape(shape, &sw, &ry);
+    return hop_tiles(g, shape) * ((nrhs + ry - 1) / ry);
+}
+
+template <typename R>
+tmh::BatchHopTask<R> hop_task(const tmh_lattice* l, int pout, void* out, const void* gauge, const void* in,
+                              const void* aux, int nrhs, const double theta[4]) {
+    using W = typename tmh::Word<R>::T;
+    tmh::BatchHopTask<R> t;
+    memset(&t, 0, sizeof t);
+    t.out = (W*)out;
+    t.in = (const W*)in;
+    t.aux = (const W*)aux;
+    t.gout = (const W*)gauge + (int64_t)pout * 36 * l->g.S;
+    t.gin = (const W*)gauge + (int64_t)(1 - pout) * 36 * l->g.S;
+    t.fstride = (int64_t)12 * l->g.S;
+    t.g = l->g;
+    t.pout = pout;
+    t.nrhs = nrhs;
+    for (int m = 0; m < 4; ++m) {
+        t.ph_re[m] = (R)cos(M_PI * theta[m]);
+        t.ph_im[m] = (R)sin(M_PI * theta[m]);
+    }
+    return t;
+}
+
+// Coefficients of the four hop steps of Qhat(sign): step 0 stores A^-1 H,
+// step 1 forms gamma_5 [A aux - H].
+template <typename R>
+void qtm_coeffs(tmh::BatchHopTask<R>& t, int step, double kappa, double mu, int sign) {
+    const double mt = 2.0 * kappa * mu * sign, D = 1.0 + mt * mt;
+    if (step == 0) {
+        t.c_re[0] = (R)(kappa / D);
+        t.c_im[0] = (R)(-kappa * mt / D);
+        t.c_re[1] = (R)(kappa / D);
+        t.c_im[1] = (R)(kappa * mt / D);
+    } else {
+        t.c_re[0] = (R)(-kappa);
+        t.c_re[1] = (R)kappa;
+        t.d_re[0] = (R)1;
+        t.d_im[0] = (R)mt;
+        t.d_re[1] = (R)-1;
+        t.d_im[1] = (R)mt;
+    }
+}
+
+tmh_status mrhs_scratch(tmh_lattice* l, int nrhs) {
+    if (nrhs <= l->mrhs_cap) return TMH_OK;
+    for (void*& p : l->mrhs) {
+        (void)hipFree(p);
+        p = nullptr;
+    }
+    l->mrhs_cap = 0;
+    for (void*& p : l->mrhs) TMH_TRY(ensure(&p, (size_t)nrhs * spinor_bytes(l, TMH_F64)));
+    l->mrhs_cap = nrhs;
+    return TMH_OK;
+}
+
+struct StreamGuard {  // a private non-null stream for graph capture, ordered after `user`
+    hipStream_t user, own = nullptr;
+    hipEvent_t ev = nullptr;
+    bool ok = false;
+    explicit StreamGuard(hipStream_t u) : user(u) {
+        ok = hipStreamCreateWithFlags(&own, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+             hipEventRecord(ev, user) == hipSuccess && hipStreamWaitEvent(own, ev, 0) == hipSuccess;
+    }
+    ~StreamGuard() {
+        if (own) {
+            (void)hipStreamSynchronize(own);
+            (void)hipStreamDestroy(own);
+        }
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+tmh_status tmh_hop_apply_mrhs(tmh_lattice* l, tmh_dir dir, void* out, const void* gauge, const void* in, int nrhs,
+                              double kappa, const double theta[4], tmh_prec prec, int shape) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(prec));
+    TMH_TRY(check_theta(theta));
+    if (dir != TMH_EO && dir != TMH_OE) return TMH_ERR_ARG;
+    if (!out || !gauge || !in || nrhs < 1 || !isfinite(kappa) || shape < -1 || shape >= tmh::kNumShapes)
+        return TMH_ERR_ARG;
+    const size_t sb = (size_t)nrhs * spinor_bytes(l, prec);
+    if (overlap(out, sb, in, sb) || overlap(out, sb, gauge, gauge_bytes(l, prec))) return TMH_ERR_ALIAS;
+    DeviceGuard guard(l->device);
+    if (shape < 0) shape = default_shape(l, nrhs, prec);
+    const int pout = dir == TMH_EO ? 0 : 1;
+    const int items = hop_items(l->g, nrhs, shape);
+    if (prec == TMH_F64) {
+        tmh::BatchHopTable<double> tab;
+        memset(&tab, 0, sizeof tab);
+        tab.ntasks = 1;
+        tab.t[0] = hop_task<double>(l, pout, out, gauge, in, nullptr, nrhs, theta);
+        tab.t[0].c_re[0] = tab.t[0].c_re[1] = kappa;
+        TMH_TRY_HIP(tmh::launch_batch_hop<double>(tab, items, shape, 0, l->stream));
+    } else {
+        tmh::BatchHopTable<float> tab;
+        memset(&tab, 0, sizeof tab);
+        tab.ntasks = 1;
+        tab.t[0] = hop_task<float>(l, pout, out, gauge, in, nullptr, nrhs, theta);
+        tab.t[0].c_re[0] = tab.t[0].c_re[1] = (float)kappa;
+        TMH_TRY_HIP(tmh::launch_batch_hop<float>(tab, items, shape, 0, l->stream));
+    }
+    return TMH_OK;
+}
+
+tmh_status tmh_batch_cg_solve(const tmh_batch_member* m, int nmem, double rel_tol, int max_iter, int shape,
+                              int use_graph, int* iters, double* true_rel_res) {
+    if (!m || nmem < 1 || nmem > tmh::kMaxBatchTasks || !iters || !true_rel_res) return TMH_ERR_ARG;
+    if (!(rel_tol > 0.0) || max_iter < 0 || shape < -1 || shape >= tmh::kNumShapes) return TMH_ERR_ARG;
+    int nsys = 0;
+    for (int k = 0; k < nmem; ++k) {
+        TMH_TRY(check_lat(m[k].lat));
+        TMH_TRY(check_theta(m[k].theta));
+        if (!m[k].x || !m[k].b || !m[k].gauge || m[k].nrhs < 1) return TMH_ERR_ARG;
+        if (!isfinite(m[k].kappa) || !isfinite(m[k].mu)) return TMH_ERR_ARG;
+        if (m[k].lat->device != m[0].lat->device) return TMH_ERR_ARG;
+        const size_t sb = (size_t)m[k].nrhs * spinor_bytes(m[k].lat, TMH_F64);
+        if (overlap(m[k].x, sb, m[k].b, sb) || overlap(m[k].x, sb, m[k].gauge, gauge_bytes(m[k].lat, TMH_F64)))
+            return TMH_ERR_ALIAS;
+        for (int j = 0; j < k; ++j)
+            if (m[j].lat == m[k].lat) return TMH_ERR_ARG;  // scratch is per lattice handle
+        nsys += m[k].nrhs;
+    }
+    tmh_lattice* l0 = m[0].lat;
+    DeviceGuard guard(l0->device);
+    if (shape < 0) shape = default_shape(l0, m[0].nrhs, TMH_F64);
+    for (int k = 0; k < nmem; ++k) TMH_TRY(mrhs_scratch(m[k].lat, m[k].nrhs));
+    // per-system partial slots, scalars, flags
+    int64_t pstride = 1;
+    int items_hop = 0, items_vec = 0;
+    tmh::BatchSysTable systab;
+    memset(&systab, 0, sizeof systab);
+    systab.ntasks = nmem;
+    for (int k = 0, s0 = 0; k < nmem; ++k) {
+        const Geo& g = m[k].lat->g;
+        systab.sys0[k] = s0;
+        systab.nrhs[k] = m[k].nrhs;
+        systab.ntile_hop[k] = hop_tiles(g, shape);
+        systab.ntile_vec[k] = tmh::batch_vec_tiles(g.Vh);
+        pstride = std::max<int64_t>(pstride, std::max(systab.ntile_hop[k], systab.ntile_vec[k]));
+        s0 += m[k].nrhs;
+    }
+    double* partial = nullptr;
+    double* scal = nullptr;
+    int* flags = nullptr;
+    double* h_scal = nullptr;
+    int* h_flags = nullptr;
+    tmh_status st = TMH_OK;
+    auto cleanup = [&]() {
+        (void)hipFree(partial);
+        (void)hipFree(scal);
+        (void)hipFree(flags);
+        if (h_scal) (void)hipHostFree(h_scal);
+        if (h_flags) (void)hipHostFree(h_flags);
+    };
+    if (hipMalloc((void**)&partial, sizeof(double) * pstride * nsys) != hipSuccess ||
+        hipMalloc((void**)&scal, sizeof(double) * tmh::kNScal * nsys) != hipSuccess ||
+        hipMalloc((void**)&flags, sizeof(int) * 2 * nsys) != hipSuccess ||
+        hipHostMalloc((void**)&h_scal, sizeof(double) * tmh::kNScal * nsys, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h_flags, sizeof(int) * 2 * nsys, hipHostMallocDefault) != hipSuccess) {
+        cleanup();
+        return TMH_ERR_NOMEM;
+    }
+    // task tables of every step
+    tmh::BatchHopTable<double> H[8];  // 0..3: CG iteration; 4..7: true residual A x
+    memset(H, 0, sizeof H);
+    tmh::BatchVecTable Vxr, Vp, Vsub, Vnb, Vcp;
+    memset(&Vxr, 0, sizeof Vxr);
+    memset(&Vp, 0, sizeof Vp);
+    memset(&Vsub, 0, sizeof Vsub);
+    memset(&Vnb, 0, sizeof Vnb);
+    memset(&Vcp, 0, sizeof Vcp);
+    for (int k = 0, s0 = 0; k < nmem; ++k) {
+        tmh_lattice* l = m[k].lat;
+        const int n = m[k].nrhs;
+        void *r = l->mrhs[0], *p = l->mrhs[1], *v = l->mrhs[2], *q = l->mrhs[3], *te = l->mrhs[4];
+        void* x = m[k].x;
+        const void* b = m[k].b;
+        const void* in0[8] = {p, te, v, te, x, te, v, te};
+        void* out0[8] = {te, v, te, q, te, v, te, q};
+        const void* aux0[8] = {nullptr, p, nullptr, v, nullptr, x, nullptr, v};
+        const int signs[8] = {+1, +1, -1, -1, +1, +1, -1, -1};
+        for (int h = 0; h < 8; ++h) {
+            auto t = hop_task<double>(l, h % 2 == 0 ? 0 : 1, out0[h], m[k].gauge, in0[h], aux0[h], n, m[k].theta);
+            qtm_coeffs(t, h % 2, m[k].kappa, m[k].mu, signs[h]);
+            t.partial = partial;
+            t.pstride = pstride;
+            t.flags = h < 4 ? flags : nullptr;
+            t.sys0 = s0;
+            t.item0 = H[h].ntasks == 0 ? 0 : H[h].t[H[h].ntasks - 1].item0 + hop_items(m[k - 1].lat->g, m[k - 1].nrhs, shape);
+            H[h].t[H[h].ntasks++] = t;
+        }
+        tmh::BatchVecTask vt;
+        memset(&vt, 0, sizeof vt);
+        vt.partial = partial;
+        vt.fstride = (int64_t)12 * l->g.S;
+        vt.pstride = pstride;
+        vt.Vh = l->g.Vh;
+        vt.S = l->g.S;
+        vt.nrhs = n;
+        vt.ntile = tmh::batch_vec_tiles(l->g.Vh);
+        vt.sys0 = s0;
+        vt.item0 = items_vec;
+        auto push = [&](tmh::BatchVecTable& T, void* a, void* bb, const void* c, const void* d) {
+            tmh::BatchVecTask u = vt;
+            u.a = (double2*)a;
+            u.b = (double2*)bb;
+            u.c = (const double2*)c;
+            u.d = (const double2*)d;
+            T.t[T.ntasks++] = u;
+        };
+        push(Vxr, x, r, p, q);
+        push(Vp, p, nullptr, r, nullptr);
+        push(Vsub, r, nullptr, b, q);
+        push(Vnb, nullptr, nullptr, b, nullptr);
+        push(Vcp, p, nullptr, r, nullptr);
+        items_vec += n * vt.ntile;
+        items_hop += hop_items(l->g, n, shape);
+        s0 += n;
+    }
+    const double tol2 = rel_tol * rel_tol;
+    tmh::batch_prepare(shape);
+    StreamGuard sg(l0->stream);
+    if (!sg.ok) {
+        cleanup();
+        return TMH_ERR_HIP;
+    }
+    hipStream_t s = sg.own;
+    auto read_back = [&]() -> tmh_status {
+        TMH_TRY_HIP(hipMemcpyAsync(h_scal, scal, sizeof(double) * tmh::kNScal * nsys, hipMemcpyDeviceToHost, s));
+        TMH_TRY_HIP(hipMemcpyAsync(h_flags, flags, sizeof(int) * 2 * nsys, hipMemcpyDeviceToHost, s));
+        TMH_TRY_HIP(hipStreamSynchronize(s));
+        return TMH_OK;
+    };
+    auto true_res = [&]() -> tmh_status {
+        for (int h = 4; h < 8; ++h) TMH_TRY_HIP(tmh::launch_batch_hop<double>(H[h], items_hop, shape, h % 2, s));
+        TMH_TRY_HIP(tmh::launch_batch_vec(2, Vsub, items_vec, scal, flags, s));
+        TMH_TRY_HIP(tmh::launch_batch_scalar(2, nsys, systab, scal, flags, partial, pstride, tol2, max_iter, s));
+        return read_back();
+    };
+    auto iteration = [&](int budget) -> hipError_t {
+        hipError_t e;
+        if ((e = tmh::launch_batch_hop<double>(H[0], items_hop, shape, 0, s)) != hipSuccess) return e;
+        if ((e = tmh::launch_batch_hop<double>(H[1], items_hop, shape, 2, s)) != hipSuccess) return e;
+        if ((e = tmh::launch_batch_scalar(0, nsys, systab, scal, flags, partial, pstride, tol2, budget, s)) != hipSuccess)
+            return e;
+        if ((e = tmh::launch_batch_hop<double>(H[2], items_hop, shape, 0, s)) != hipSuccess) return e;
+        if ((e = tmh::launch_batch_hop<double>(H[3], items_hop, shape, 1, s)) != hipSuccess) return e;
+        if ((e = tmh::launch_batch_vec(0, Vxr, items_vec, scal, flags, s)) != hipSuccess) return e;
+        if ((e = tmh::launch_batch_scalar(1, nsys, systab, scal, flags, partial, pstride, tol2, budget, s)) != hipSuccess)
+            return e;
+        return tmh::launch_batch_vec(1, Vp, items_vec, scal, flags, s);
+    };
+    std::vector<int> total(nsys, 0);
+    std::vector<double> bb(nsys), res(nsys, 0.0);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_budget = -1;
+    do {
+        // |b|^2 per system
+        if (tmh::launch_batch_vec(3, Vnb, items_vec, scal, flags, s) != hipSuccess ||
+            tmh::launch_batch_scalar(4, nsys, systab, scal, flags, partial, pstride, tol2, max_iter, s) != hipSuccess) {
+            st = TMH_ERR_HIP;
+            break;
+        }
+        if ((st = read_back()) != TMH_OK) break;
+        for (int k = 0; k < nsys; ++k) bb[k] = h_scal[k * tmh::kNScal + tmh::kBB];
+        if ((st = true_res()) != TMH_OK) break;
+        int it_done = 0;
+        for (int restart = 0;; ++restart) {
+            bool all = true;
+            for (int k = 0; k < nsys; ++k) {
+                const double rr = h_scal[k * tmh::kNScal + tmh::kNorm];
+                res[k] = bb[k] > 0.0 ? sqrt(rr / bb[k]) : 0.0;
+                if (res[k] > rel_tol) all = false;
+            }
+            if (all || restart > 3 || it_done >= max_iter) break;
+            const int budget = max_iter - it_done;
+            if (tmh::launch_batch_scalar(3, nsys, systab, scal, flags, partial, pstride, tol2, budget, s) != hipSuccess ||
+                tmh::launch_batch_vec(4, Vcp, items_vec, scal, flags, s) != hipSuccess) {
+                st = TMH_ERR_HIP;
+                break;
+            }
+            if (use_graph && graph_budget != budget) {
+                if (exec) (void)hipGraphExecDestroy(exec);
+                if (graph) (void)hipGraphDestroy(graph);
+                exec = nullptr;
+                graph = nullptr;
+                if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                    st = TMH_ERR_HIP;
+                    break;
+                }
+                const hipError_t e = iteration(budget);
+                if (hipStreamEndCapture(s, &graph) != hipSuccess || e != hipSuccess ||
+                    hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                    st = TMH_ERR_HIP;
+                    break;
+                }
+                graph_budget = budget;
+            }
+            bool running = true;
+            while (running) {
+                for (int c = 0; c < kChunk; ++c) {
+                    const hipError_t e = use_graph ? hipGraphLaunch(exec, s) : iteration(budget);
+                    if (e != hipSuccess) {
+                        st = TMH_ERR_HIP;
+                        break;
+                    }
+                }
+                if (st != TMH_OK || (st = read_back()) != TMH_OK) break;
+                running = false;
+                for (int k = 0; k < nsys; ++k)
+                    if (!h_flags[2 * k]) running = true;
+            }
+            if (st != TMH_OK) break;
+            int mx = 0;
+            for (int k = 0; k < nsys; ++k) {
+                total[k] += h_flags[2 * k + 1];
+                mx = std::max(mx, h_flags[2 * k + 1]);
+            }
+            it_done += mx;
+            if ((st = true_res()) != TMH_OK) break;
+        }
+    } while (false);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    bool conv = st == TMH_OK;
+    for (int k = 0; k < nsys; ++k) {
+        iters[k] = total[k];
+        true_rel_res[k] = res[k];
+        if (res[k] > rel_tol) conv = false;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && st == TMH_OK) st = TMH_ERR_HIP;
+    cleanup();
+    if (st != TMH_OK) return st;
+    return conv ? TMH_OK : TMH_ERR_NOT_CONVERGED;
+}
+
+tmh_status tmh_autotune_mrhs(tmh_lattice* l, const void* gauge, int nrhs, tmh_prec prec, const char* cache_path,
+                             int* best_shape, double* best_us) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(prec));
+    if (!gauge || nrhs < 1 || nrhs > 16 || !best_shape || !best_us) return TMH_ERR_ARG;
+    DeviceGuard guard(l->device);
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, l->device) == hipSuccess) arch = prop.gcnArchName;
+    const size_t sp = arch.find(':');
+    if (sp != std::string::npos) arch = arch.substr(0, sp);
+    char key[256];
+    snprintf(key, sizeof key, "%s %dx%dx%dx%d %s %d", arch.c_str(), l->dims[0], l->dims[1], l->dims[2], l->dims[3],
+             prec == TMH_F64 ? "f64" : "f32", nrhs);
+    if (cache_path) {
+        if (FILE* f = fopen(cache_path, "r")) {
+            char line[512];
+            while (fgets(line, sizeof line, f)) {
+                int sh = -1;
+                double us = 0.0;
+                const size_t kl = strlen(key);
+                if (strncmp(line, key, kl) == 0 && line[kl] == ' ' && sscanf(line + kl, " %d %lf", &sh, &us) == 2 &&
+                    sh >= 0 && sh < tmh::kNumShapes) {
+                    *best_shape = sh;
+                    *best_us = us;
+                }
+            }
+            fclose(f);
+            if (*best_shape >= 0 && *best_shape < tmh::kNumShapes && *best_us > 0.0) {
+                l->tuned[prec][nrhs] = *best_shape;
+                return TMH_OK;
+            }
+        }
+    }
+    // time every shape on scratch fields
+    void *in = nullptr, *out = nullptr;
+    const size_t sb = (size_t)nrhs * spinor_bytes(l, prec);
+    if (hipMalloc(&in, sb) != hipSuccess || hipMalloc(&out, sb) != hipSuccess) {
+        (void)hipFree(in);
+        return TMH_ERR_NOMEM;
+    }
+    tmh_status st = TMH_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double best = 1e300;
+    int bs = -1;
+    const double theta[4] = {1.0, 0.0, 0.0, 0.0};
+    if (hipMemsetAsync(in, 0, sb, l->stream) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        st = TMH_ERR_HIP;
+    for (int sh = 0; sh < tmh::kNumShapes && st == TMH_OK; ++sh) {
+        for (int w = 0; w < 2 && st == TMH_OK; ++w)
+            st = tmh_hop_apply_mrhs(l, TMH_EO, out, gauge, in, nrhs, 0.1, theta, prec, sh);
+        if (st != TMH_OK) break;
+        const int reps = 5;
+        if (hipEventRecord(e0, l->stream) != hipSuccess) st = TMH_ERR_HIP;
+        for (int k = 0; k < reps && st == TMH_OK; ++k)
+            st = tmh_hop_apply_mrhs(l, k % 2 ? TMH_OE : TMH_EO, out, gauge, in, nrhs, 0.1, theta, prec, sh);
+        float ms = 0.f;
+        if (st == TMH_OK && (hipEventRecord(e1, l->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = TMH_ERR_HIP;
+        const double us = 1e3 * ms / reps;
+        if (st == TMH_OK && us < best) {
+            best = us;
+            bs = sh;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(l->stream);
+    (void)hipFree(in);
+    (void)hipFree(out);
+    if (st != TMH_OK) return st;
+    *best_shape = bs;
+    *best_us = best;
+    l->tuned[prec][nrhs] = bs;
+    if (cache_path) {
+        if (FILE* f = fopen(cache_path, "a")) {
+            fprintf(f, "%s %d %.3f\n", key, bs, best);
+            fclose(f);
+        }
+    }
+    return TMH_OK;
 }
 
 tmh_status tmh_gauge_export(tmh_lattice* l, double* dst, const void* src, tmh_prec prec) {

@@ -1,0 +1,372 @@
+// Batched operators: many right-hand sides on several lattices in one
+// persistent launch per operator step.
+//
+// A batch is a list of tasks, one per lattice, each with nrhs fields stored
+// one after another (field r of a task at base + r * fstride words).  The
+// work of a launch is a list of items, task after task; an item is a tile of
+// 64*SW sites of one lattice for a group of RY right-hand sides, so the RY
+// waves-groups of a workgroup read the same links for the same sites and
+// the second and later reads of each link come from L1/L2.  A fixed
+// (persistent) grid walks the items: XCD k takes one contiguous range of
+// items, its workgroups stride through it.
+//
+// BLAS-1 and reductions run per system (task, rhs); every system keeps its
+// own CG scalars and flags, and a system whose flag is set is skipped, so the
+// batch keeps iterating until its last system converges.
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+#include "hop_body.h"
+#include "kernels.h"
+
+namespace tmh {
+
+void batch_shape(int shape, int* sw, int* ry) {
+    static const int SW[kNumShapes] = {4, 2, 1, 2, 1};
+    static const int RY[kNumShapes] = {1, 2, 4, 4, 12};
+    *sw = SW[shape];
+    *ry = RY[shape];
+}
+
+namespace {
+
+// Range of items of XCD k and the stride of its workgroups.
+struct XcdRange {
+    int start, count, k, nper;
+};
+__device__ __forceinline__ XcdRange xcd_range(int nitems) {
+    XcdRange r;
+    const int x = blockIdx.x % kXcds;
+    r.k = blockIdx.x / kXcds;
+    r.nper = gridDim.x / kXcds;
+    const int q = nitems / kXcds, m = nitems % kXcds;
+    r.start = x * q + (x < m ? x : m);
+    r.count = q + (x < m ? 1 : 0);
+    return r;
+}
+
+template <typename Table> __device__ __forceinline__ int find_task(const Table& tab, int item) {
+    int t = 0;
+    while (t + 1 < tab.ntasks && tab.t[t + 1].item0 <= item) ++t;
+    return t;
+}
+
+template <typename R, int MODE, int SW, int RY, bool PIPE>
+__global__ void __launch_bounds__(64 * SW * RY) batch_hop_kernel(BatchHopTable<R> tasks, int nitems) {
+    constexpr int NSL = 64 * SW;
+    const int lane_site = threadIdx.x % NSL;
+    const int slot = threadIdx.x / NSL;
+    __shared__ double red[SW * RY];
+    const XcdRange xr = xcd_range(nitems);
+    for (int it = xr.k; it < xr.count; it += xr.nper) {
+        const int item = xr.start + it;
+        const BatchHopTask<R>& T = tasks.t[find_task(tasks, item)];
+        const int local = item - T.item0;
+        const int ngroups = (T.nrhs + RY - 1) / RY;
+        const int tile = local / ngroups;
+        const int rhs = (local - tile * ngroups) * RY + slot;
+        const int i = tile * NSL + lane_site;
+        double nrm = 0.0;
+        const bool live = rhs < T.nrhs && !(T.flags && T.flags[2 * (T.sys0 + rhs)]);
+        if (live && i < T.g.Vh) {
+            HopArgs<R> a;
+            a.in = T.in + rhs * T.fstride;
+            a.gout = T.gout;
+            a.gin = T.gin;
+            a.g = T.g;
+            a.pout = T.pout;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                a.ph_re[m] = T.ph_re[m];
+                a.ph_im[m] = T.ph_im[m];
+            }
+            int c[4], lex;
+            site_coords(T.g, i, T.pout, c, lex);
+            cx<R> acc[4][3];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) acc[s][k] = mk<R>(0, 0);
+            const SiteNb n = site_neighbours(T.g, c, lex);
+            // links are shared by the RY right-hand sides: cache them unless RY == 1
+            hop_site<R, PIPE, (RY == 1 ? kLinkAux : 0)>(acc, a, n, i);
+            const int S = T.g.S;
+            typename Word<R>::T* out = T.out + rhs * T.fstride;
+            const typename Word<R>::T* aux = T.aux + rhs * T.fstride;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const cx<R> cc = mk<R>(T.c_re[s >> 1], T.c_im[s >> 1]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t comp = (int64_t)(3 * s + k) * S;
+                    cx<R> o = cc * acc[s][k];
+                    if constexpr (MODE >= 1)
+                        o += mk<R>(T.d_re[s >> 1], T.d_im[s >> 1]) * bload<R, out_aux<R>()>(aux + comp, S, i);
+                    if constexpr (MODE == 2) nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+                    bstore<R, out_aux<R>()>(out + comp, S, i, o);
+                }
+            }
+        }
+        if constexpr (MODE == 2) {
+            // per right-hand side: the SW waves of a slot sum their sites
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+            __syncthreads();
+            if (lane_site == 0 && rhs < T.nrhs) {
+                double s = 0.0;
+#pragma unroll
+                for (int w = 0; w < SW; ++w) s += red[slot * SW + w];
+                T.partial[(int64_t)(T.sys0 + rhs) * T.pstride + tile] = s;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------- BLAS-1
+
+constexpr int kVecTile = kBlock;  // sites per item of the vector kernels
+
+__device__ __forceinline__ bool sys_done(const int* flags, int sys) { return flags && flags[2 * sys] != 0; }
+
+// op 0: a += alpha c, b -= alpha d, partial |b|^2        (x, r, p, q)
+// op 1: a = c + beta a                                  (p, r)
+// op 2: a = c - d, partial |a|^2                        (r, b, q)
+// op 3: partial |c|^2
+// op 4: a = c                                           (copy)
+template <int OP>
+__global__ void __launch_bounds__(kBlock) batch_vec_kernel(BatchVecTable tasks, int nitems,
+                                                           const double* __restrict__ scal, const int* flags) {
+    const XcdRange xr = xcd_range(nitems);
+    for (int it = xr.k; it < xr.count; it += xr.nper) {
+        const int item = xr.start + it;
+        const BatchVecTask& T = tasks.t[find_task(tasks, item)];
+        const int local = item - T.item0;
+        const int rhs = local / T.ntile, tile = local - rhs * T.ntile;
+        const int sys = T.sys0 + rhs;
+        const bool skip = (OP <= 1) && sys_done(flags, sys);
+        const int i = tile * kVecTile + threadIdx.x;
+        const int64_t base = rhs * T.fstride;
+        double nrm = 0.0;
+        if (!skip && i < T.Vh) {
+            const double alpha = (OP == 0) ? scal[sys * kNScal + kAlpha] : 0.0;
+            const double beta = (OP == 1) ? scal[sys * kNScal + kBeta] : 0.0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const int64_t k = base + (int64_t)c * T.S + i;
+                if constexpr (OP == 0) {
+                    double2 x = T.a[k], r = T.b[k];
+                    const double2 p = T.c[k], q = T.d[k];
+                    x.x += alpha * p.x;
+                    x.y += alpha * p.y;
+                    r.x -= alpha * q.x;
+                    r.y -= alpha * q.y;
+                    T.a[k] = x;
+                    T.b[k] = r;
+                    nrm += r.x * r.x + r.y * r.y;
+                } else if constexpr (OP == 1) {
+                    double2 p = T.a[k];
+                    const double2 r = T.c[k];
+                    p.x = r.x + beta * p.x;
+                    p.y = r.y + beta * p.y;
+                    T.a[k] = p;
+                } else if constexpr (OP == 2) {
+                    const double2 b = T.c[k], q = T.d[k];
+                    const double2 r = make_double2(b.x - q.x, b.y - q.y);
+                    T.a[k] = r;
+                    nrm += r.x * r.x + r.y * r.y;
+                } else if constexpr (OP == 3) {
+                    const double2 v = T.c[k];
+                    nrm += v.x * v.x + v.y * v.y;
+                } else {
+                    T.a[k] = T.c[k];
+                }
+            }
+        }
+        if constexpr (OP == 0 || OP == 2 || OP == 3) {
+            // skipped systems still write a partial (zero) to keep the sums defined
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+            __shared__ double red[kBlock / 64];
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+            __syncthreads();
+            if (threadIdx.x == 0 && !skip) {
+                double s = 0.0;
+#pragma unroll
+                for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+                T.partial[(int64_t)sys * T.pstride + tile] = s;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// -------------------------------------------------------- per-system scalars
+
+// Sum of n partials of system `sys` by one workgroup (fixed order).
+__device__ __forceinline__ double sys_sum(const double* __restrict__ partial, int64_t pstride, int sys, int n) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += kBlock) s += partial[(int64_t)sys * pstride + k];
+    return block_sum(s);
+}
+
+// op 0 (alpha): pq = sum(hop partials), alpha = rr / pq
+// op 1 (beta):  rr' = sum(vec partials), beta = rr'/rr, rr = rr', iterations, done
+// op 2 (norm):  scal[kNorm] = sum(vec partials)
+// op 3 (init):  rr = sum(vec partials); stop = tol^2 scal[kBB]; done = rr <= stop; iterations = 0
+// op 4 (bb):    scal[kBB] = sum(vec partials)
+template <int OP>
+__global__ void __launch_bounds__(kBlock) batch_scalar_kernel(BatchSysTable sys, double* scal, int* flags,
+                                                              const double* __restrict__ partial, int64_t pstride,
+                                                              double tol2, int max_iter) {
+    const int s = blockIdx.x;
+    if ((OP == 0 || OP == 1) && flags[2 * s]) return;
+    int t = 0;
+    while (t + 1 < sys.ntasks && sys.sys0[t + 1] <= s) ++t;
+    const int n = OP == 0 ? sys.ntile_hop[t] : sys.ntile_vec[t];
+    const double v = sys_sum(partial, pstride, s, n);
+    if (threadIdx.x != 0) return;
+    double* sc = scal + (int64_t)s * kNScal;
+    if constexpr (OP == 0) {
+        sc[kPQ] = v;
+        sc[kAlpha] = sc[kRR] / v;
+    } else if constexpr (OP == 1) {
+        sc[kBeta] = v / sc[kRR];
+        sc[kRR] = v;
+        const int it = flags[2 * s + 1] + 1;
+        flags[2 * s + 1] = it;
+        if (v <= sc[kStop] || it >= max_iter) flags[2 * s] = 1;
+    } else if constexpr (OP == 2) {
+        sc[kNorm] = v;
+    } else if constexpr (OP == 4) {
+        sc[kBB] = v;
+    } else {
+        sc[kRR] = v;
+        sc[kStop] = tol2 * sc[kBB];
+        flags[2 * s] = v <= sc[kStop] ? 1 : 0;
+        flags[2 * s + 1] = 0;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+template <typename R, int MODE, int SW, int RY>
+static const void* batch_hop_fn() {
+    constexpr bool pipe = false;  // the persistent loop leaves no room for two register sets
+    return reinterpret_cast<const void*>(&batch_hop_kernel<R, MODE, SW, RY, pipe>);
+}
+
+template <typename R, int MODE>
+static const void* batch_hop_sel(int shape) {
+    switch (shape) {
+        case kShape4x1: return batch_hop_fn<R, MODE, 4, 1>();
+        case kShape2x2: return batch_hop_fn<R, MODE, 2, 2>();
+        case kShape1x4: return batch_hop_fn<R, MODE, 1, 4>();
+        case kShape2x4: return batch_hop_fn<R, MODE, 2, 4>();
+        default: return batch_hop_fn<R, MODE, 1, 12>();
+    }
+}
+
+template <typename R>
+static const void* batch_hop_kernel_ptr(int shape, int mode) {
+    return mode == 0 ? batch_hop_sel<R, 0>(shape) : (mode == 1 ? batch_hop_sel<R, 1>(shape)
+                                                                : batch_hop_sel<R, 2>(shape));
+}
+
+// Workgroups of `fn` the device holds at once (CUs x resident workgroups per
+// CU), queried once per kernel and device and remembered, so that launches
+// made while a stream is being captured into a graph query nothing.
+static int resident_blocks(const void* fn, int threads) {
+    struct Entry {
+        const void* fn;
+        int dev, threads, blocks;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    for (const Entry& e : cache)
+        if (e.fn == fn && e.dev == dev && e.threads == threads) return e.blocks;
+    int ncu = 256, per = 1;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, 0) != hipSuccess || per < 1) per = 1;
+    cache.push_back({fn, dev, threads, ncu * per});
+    return ncu * per;
+}
+
+// Persistent grid: all the workgroups that fit on the device at once, a
+// multiple of the XCD count, no more than the items need.
+static int persistent_grid(const void* fn, int threads, int nitems) {
+    int grid = resident_blocks(fn, threads);
+    const int need = (nitems + kXcds - 1) / kXcds * kXcds;
+    if (grid > need) grid = need;
+    grid = (grid + kXcds - 1) / kXcds * kXcds;
+    return grid < kXcds ? kXcds : grid;
+}
+
+template <typename R>
+hipError_t launch_batch_hop(const BatchHopTable<R>& tasks, int nitems, int shape, int mode, hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    int sw, ry;
+    batch_shape(shape, &sw, &ry);
+    const int threads = 64 * sw * ry;
+    const void* fn = batch_hop_kernel_ptr<R>(shape, mode);
+    const int grid = persistent_grid(fn, threads, nitems);
+    BatchHopTable<R> tab = tasks;
+    void* args[] = {(void*)&tab, (void*)&nitems};
+    return hipLaunchKernel(fn, dim3(grid), dim3(threads), args, 0, s);
+}
+
+template <int OP> static const void* vec_fn() { return reinterpret_cast<const void*>(&batch_vec_kernel<OP>); }
+
+hipError_t launch_batch_vec(int op, const BatchVecTable& tasks, int nitems, const double* scal, const int* flags,
+                            hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    const void* fn = op == 0 ? vec_fn<0>() : op == 1 ? vec_fn<1>() : op == 2 ? vec_fn<2>() : op == 3 ? vec_fn<3>()
+                                                                                                : vec_fn<4>();
+    const int grid = persistent_grid(fn, kBlock, nitems);
+    BatchVecTable tab = tasks;
+    void* args[] = {(void*)&tab, (void*)&nitems, (void*)&scal, (void*)&flags};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, s);
+}
+
+hipError_t launch_batch_scalar(int op, int nsys, const BatchSysTable& sys, double* scal, int* flags,
+                               const double* partial, int64_t pstride, double tol2, int max_iter, hipStream_t s) {
+    if (nsys == 0) return hipSuccess;
+    switch (op) {
+        case 0: hipLaunchKernelGGL(batch_scalar_kernel<0>, dim3(nsys), dim3(kBlock), 0, s, sys, scal, flags, partial,
+                                   pstride, tol2, max_iter); break;
+        case 1: hipLaunchKernelGGL(batch_scalar_kernel<1>, dim3(nsys), dim3(kBlock), 0, s, sys, scal, flags, partial,
+                                   pstride, tol2, max_iter); break;
+        case 2: hipLaunchKernelGGL(batch_scalar_kernel<2>, dim3(nsys), dim3(kBlock), 0, s, sys, scal, flags, partial,
+                                   pstride, tol2, max_iter); break;
+        case 3: hipLaunchKernelGGL(batch_scalar_kernel<3>, dim3(nsys), dim3(kBlock), 0, s, sys, scal, flags, partial,
+                                   pstride, tol2, max_iter); break;
+        default: hipLaunchKernelGGL(batch_scalar_kernel<4>, dim3(nsys), dim3(kBlock), 0, s, sys, scal, flags,
+                                    partial, pstride, tol2, max_iter); break;
+    }
+    return hipGetLastError();
+}
+
+int batch_vec_tiles(int Vh) { return (Vh + kVecTile - 1) / kVecTile; }
+
+void batch_prepare(int shape) {
+    int sw, ry;
+    batch_shape(shape, &sw, &ry);
+    for (int mode = 0; mode < 3; ++mode) {
+        (void)resident_blocks(batch_hop_kernel_ptr<double>(shape, mode), 64 * sw * ry);
+        (void)resident_blocks(batch_hop_kernel_ptr<float>(shape, mode), 64 * sw * ry);
+    }
+    const void* v[5] = {vec_fn<0>(), vec_fn<1>(), vec_fn<2>(), vec_fn<3>(), vec_fn<4>()};
+    for (const void* f : v) (void)resident_blocks(f, kBlock);
+}
+
+template hipError_t launch_batch_hop<double>(const BatchHopTable<double>&, int, int, int, hipStream_t);
+template hipError_t launch_batch_hop<float>(const BatchHopTable<float>&, int, int, int, hipStream_t);
+
+}  // namespace tmh

@@ -17,224 +17,9 @@
 #include "common.h"
 #include "kernels.h"
 
-// Compile-time tuning of the hopping kernel:
-//   TMH_HOP_WAVES     minimum waves per SIMD the register allocation must
-//                     allow (0: compiler's choice)
-//   TMH_HOP_NT_LINKS  load links with non-temporal hints (each link is read
-//                     once per application, so it need not displace the
-//                     neighbour spinors in the caches)
-//   TMH_XCD_REMAP     give every XCD one contiguous range of sites
-//   TMH_HOP_SCHED     keep the instruction scheduler from moving work across
-//                     the boundaries between the 8 terms
-//   TMH_HOP_PIPE      software-pipeline the terms: load term t+1, then
-//                     compute term t
-//   TMH_HOP_NT_STORE  FP64 only: store the output (and read the fused
-//                     epilogue's input at the output site) with non-temporal
-//                     hints (measured: a gain in FP64, a small loss in FP32)
-//   TMH_HOP_BLOCK     threads per workgroup
-#ifndef TMH_HOP_WAVES
-#define TMH_HOP_WAVES 0
-#endif
-#ifndef TMH_HOP_NT_LINKS
-#define TMH_HOP_NT_LINKS 1
-#endif
-#ifndef TMH_XCD_REMAP
-#define TMH_XCD_REMAP 1
-#endif
-#ifndef TMH_HOP_SCHED
-#define TMH_HOP_SCHED 1
-#endif
-#ifndef TMH_HOP_PIPE
-#define TMH_HOP_PIPE 1
-#endif
-#ifndef TMH_HOP_NT_STORE
-#define TMH_HOP_NT_STORE 1
-#endif
-#ifndef TMH_HOP_BLOCK
-#define TMH_HOP_BLOCK 256
-#endif
-#if TMH_HOP_WAVES > 0
-#define TMH_HOP_ATTR __attribute__((amdgpu_waves_per_eu(TMH_HOP_WAVES, 8)))
-#else
-#define TMH_HOP_ATTR
-#endif
+#include "hop_body.h"
 
 namespace tmh {
-
-// Cache policy of the link loads: each link is read once per application,
-// so a non-temporal hint keeps it from displacing neighbour spinors.
-constexpr int kLinkAux = TMH_HOP_NT_LINKS ? 2 : 0;
-template <typename R> constexpr int out_aux() { return (TMH_HOP_NT_STORE && sizeof(R) == 8) ? 2 : 0; }
-constexpr int kHopBlock = TMH_HOP_BLOCK;
-
-// Data one of the 8 terms needs: the neighbour's spinor and the link.
-template <typename R> struct TermData {
-    cx<R> psi[4][3];
-    cx<R> u[3][3];
-};
-
-template <typename R>
-__device__ __forceinline__ void load_term(TermData<R>& d, const typename Word<R>::T* __restrict__ in,
-                                          const typename Word<R>::T* __restrict__ link, int S, int jn, int jl) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) d.psi[s][a] = bload<R>(in + (int64_t)(3 * s + a) * S, S, jn);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) d.u[k / 3][k % 3] = bload<R, kLinkAux>(link + (int64_t)k * S, S, jl);
-}
-
-// One of the 8 terms: DIR = +1 adds (1 - gamma_mu) U_mu(x) psi(x+mu),
-// DIR = -1 adds (1 + gamma_mu) U_mu(x-mu)^dagger psi(x-mu).
-template <typename R, int MU, int DIR>
-__device__ __forceinline__ void add_term(cx<R> (&acc)[4][3], const TermData<R>& d, bool wrap, cx<R> ph) {
-    // half-spinor h = psi_up - DIR e_mu psi_dn
-    cx<R> h[2][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        cx<R> e0, e1;
-        e_lower<R, MU>(d.psi[2][a], d.psi[3][a], e0, e1);
-        if constexpr (DIR > 0) {
-            h[0][a] = d.psi[0][a] - e0;
-            h[1][a] = d.psi[1][a] - e1;
-        } else {
-            h[0][a] = d.psi[0][a] + e0;
-            h[1][a] = d.psi[1][a] + e1;
-        }
-    }
-    // boundary phase, branch-free so that each term stays one basic block
-    const cx<R> eta = wrap ? ph : mk<R>(1, 0);
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) h[s][a] = h[s][a] * eta;
-    // g = U h (forward) or U^dagger h (backward)
-    cx<R> g[2][3];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if constexpr (DIR > 0)
-                g[s][a] = d.u[a][0] * h[s][0] + d.u[a][1] * h[s][1] + d.u[a][2] * h[s][2];
-            else
-                g[s][a] = cmul(d.u[0][a], h[s][0]) + cmul(d.u[1][a], h[s][1]) + cmul(d.u[2][a], h[s][2]);
-        }
-    // upper spins take g, lower spins take -DIR e_mu^dagger g
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        acc[0][a] += g[0][a];
-        acc[1][a] += g[1][a];
-        cx<R> f0, f1;
-        edag<R, MU>(g[0][a], g[1][a], f0, f1);
-        if constexpr (DIR > 0) {
-            acc[2][a] -= f0;
-            acc[3][a] -= f1;
-        } else {
-            acc[2][a] += f0;
-            acc[3][a] += f1;
-        }
-    }
-}
-
-// Site geometry shared by the 8 terms.
-struct SiteNb {
-    int jn[8];     // neighbour even-odd index, term t = 2*mu + (backward ? 1 : 0)
-    unsigned wrap; // bit t set when term t crosses the boundary
-};
-
-__device__ __forceinline__ SiteNb site_neighbours(const Geo& g, const int c[4], int lex) {
-    SiteNb n;
-    n.wrap = 0;
-    int stride = 1;
-#pragma unroll
-    for (int mu = 3; mu >= 0; --mu) {
-        const int Lm = g.L[mu];
-        const bool wf = c[mu] == Lm - 1, wb = c[mu] == 0;
-        n.jn[2 * mu] = (wf ? lex - (Lm - 1) * stride : lex + stride) >> 1;
-        n.jn[2 * mu + 1] = (wb ? lex + (Lm - 1) * stride : lex - stride) >> 1;
-        n.wrap |= (wf ? 1u : 0u) << (2 * mu);
-        n.wrap |= (wb ? 1u : 0u) << (2 * mu + 1);
-        stride *= Lm;
-    }
-    return n;
-}
-
-// Term t = 2*mu + b: forward (b = 0) uses U_mu(x) from the output parity at
-// the site's own index i; backward (b = 1) uses U_mu(x - mu) from the input
-// parity at the neighbour's index.
-template <typename R, int T>
-__device__ __forceinline__ void load_t(TermData<R>& d, const HopArgs<R>& a, const SiteNb& n, int i) {
-    constexpr int MU = T / 2;
-    if constexpr (T % 2 == 0)
-        load_term<R>(d, a.in, a.gout + (int64_t)MU * 9 * a.g.S, a.g.S, n.jn[T], i);
-    else
-        load_term<R>(d, a.in, a.gin + (int64_t)MU * 9 * a.g.S, a.g.S, n.jn[T], n.jn[T]);
-}
-
-template <typename R, int T>
-__device__ __forceinline__ void add_t(cx<R> (&acc)[4][3], const TermData<R>& d, const HopArgs<R>& a,
-                                      const SiteNb& n) {
-    constexpr int MU = T / 2;
-    const bool wrap = (n.wrap >> T) & 1u;
-    if constexpr (T % 2 == 0)
-        add_term<R, MU, +1>(acc, d, wrap, mk<R>(a.ph_re[MU], a.ph_im[MU]));
-    else
-        add_term<R, MU, -1>(acc, d, wrap, mk<R>(a.ph_re[MU], -a.ph_im[MU]));
-}
-
-#if TMH_HOP_SCHED
-#define TMH_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
-#else
-#define TMH_SCHED_FENCE() ((void)0)
-#endif
-
-// Sum of the 8 terms.  TMH_HOP_PIPE = 1 loads term t+1 before computing term t
-// (two register sets); otherwise each term is loaded and consumed in turn.
-template <typename R>
-__device__ __forceinline__ void hop_site(cx<R> (&acc)[4][3], const HopArgs<R>& a, const SiteNb& n, int i) {
-#if TMH_HOP_PIPE
-    TermData<R> d0, d1;
-    load_t<R, 0>(d0, a, n, i);
-    TMH_SCHED_FENCE();
-    load_t<R, 1>(d1, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<R, 0>(acc, d0, a, n);
-    TMH_SCHED_FENCE();
-    load_t<R, 2>(d0, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<R, 1>(acc, d1, a, n);
-    TMH_SCHED_FENCE();
-    load_t<R, 3>(d1, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<R, 2>(acc, d0, a, n);
-    TMH_SCHED_FENCE();
-    load_t<R, 4>(d0, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<R, 3>(acc, d1, a, n);
-    TMH_SCHED_FENCE();
-    load_t<R, 5>(d1, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<R, 4>(acc, d0, a, n);
-    TMH_SCHED_FENCE();
-    load_t<R, 6>(d0, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<R, 5>(acc, d1, a, n);
-    TMH_SCHED_FENCE();
-    load_t<R, 7>(d1, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<R, 6>(acc, d0, a, n);
-    TMH_SCHED_FENCE();
-    add_t<R, 7>(acc, d1, a, n);
-#else
-    TermData<R> d;
-#define TMH_TERM(T)              \
-    load_t<R, T>(d, a, n, i);    \
-    add_t<R, T>(acc, d, a, n);   \
-    TMH_SCHED_FENCE();
-    TMH_TERM(0) TMH_TERM(1) TMH_TERM(2) TMH_TERM(3) TMH_TERM(4) TMH_TERM(5) TMH_TERM(6) TMH_TERM(7)
-#undef TMH_TERM
-#endif
-}
 
 template <typename R, int MODE>
 __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> a) {
@@ -255,7 +40,7 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> 
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc[s][k] = mk<R>(0, 0);
         const SiteNb n = site_neighbours(a.g, c, lex);
-        hop_site<R>(acc, a, n, i);
+        hop_site<R, TMH_HOP_PIPE != 0>(acc, a, n, i);
         const int S = a.g.S;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {

@@ -65,7 +65,7 @@ hipError_t launch_reduce(double* out, const double* partial, int n, const int* d
 
 // CG building blocks on one parity.  scal[] holds the device scalars
 // (see CgScal), flags[] = {done, iterations}.
-enum CgScal { kRR = 0, kPQ = 1, kAlpha = 2, kBeta = 3, kStop = 4, kRRNew = 5, kNorm = 6, kNScal = 8 };
+enum CgScal { kRR = 0, kPQ = 1, kAlpha = 2, kBeta = 3, kStop = 4, kRRNew = 5, kNorm = 6, kBB = 7, kNScal = 8 };
 template <typename R>
 hipError_t launch_cg_alpha(double* scal, const double* partial, int n, int* flags, hipStream_t s);
 template <typename R>
@@ -96,5 +96,66 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t nbytes, hipStre
 // given partials, flags = {0, 0}.
 hipError_t launch_cg_init(double* scal, const double* partial, int n, int* flags, double stop,
                           hipStream_t s);
+
+// ----------------------------------------------------------------- batches
+// (batch.hip) A batch task is one lattice with nrhs fields stored back to
+// back; systems are numbered across tasks (sys0 = first system of a task),
+// CG scalars live at scal[sys * kNScal], flags at flags[2 * sys].
+enum BatchShapeId { kShape4x1 = 0, kShape2x2 = 1, kShape1x4 = 2, kShape2x4 = 3, kShape1x12 = 4, kNumShapes = 5 };
+void batch_shape(int shape, int* sites_waves, int* rhs_per_group);
+
+template <typename R> struct BatchHopTask {
+    typename Word<R>::T* out;
+    const typename Word<R>::T* in;
+    const typename Word<R>::T* aux;
+    const typename Word<R>::T* gout;
+    const typename Word<R>::T* gin;
+    double* partial;       // MODE 2: partial[sys * pstride + tile]
+    const int* flags;      // optional: skip system when flags[2 * sys] != 0
+    int64_t fstride;       // words between the fields of consecutive right-hand sides
+    int64_t pstride;
+    Geo g;
+    int pout, nrhs, sys0, item0;
+    R ph_re[4], ph_im[4], c_re[2], c_im[2], d_re[2], d_im[2];
+};
+constexpr int kMaxBatchTasks = 8;  // lattices per batch (task tables travel as kernel arguments)
+template <typename R> struct BatchHopTable {
+    BatchHopTask<R> t[kMaxBatchTasks];
+    int ntasks;
+};
+template <typename R>
+hipError_t launch_batch_hop(const BatchHopTable<R>& tasks, int nitems, int shape, int mode, hipStream_t s);
+
+struct BatchVecTask {
+    double2* a;
+    double2* b;
+    const double2* c;
+    const double2* d;
+    double* partial;
+    int64_t fstride, pstride;
+    int Vh, S, nrhs, ntile, sys0, item0;
+};
+// op 0: x += alpha p, r -= alpha q (+|r|^2); 1: p = r + beta p; 2: r = b - q (+|r|^2);
+// 3: |c|^2 partials; 4: a = c
+struct BatchVecTable {
+    BatchVecTask t[kMaxBatchTasks];
+    int ntasks;
+};
+hipError_t launch_batch_vec(int op, const BatchVecTable& tasks, int nitems, const double* scal, const int* flags,
+                            hipStream_t s);
+int batch_vec_tiles(int Vh);
+// Queries (once) the resident workgroups of every batch kernel of this shape,
+// so that later launches, also under graph capture, query nothing.
+void batch_prepare(int shape);
+
+// Partial-sum counts per task: systems sys0 .. sys0 + nrhs - 1 of task k sum
+// ntile_hop partials after a MODE 2 hop and ntile_vec after a vector kernel.
+struct BatchSysTable {
+    int sys0[kMaxBatchTasks], nrhs[kMaxBatchTasks], ntile_hop[kMaxBatchTasks], ntile_vec[kMaxBatchTasks];
+    int ntasks;
+};
+// op 0: alpha; 1: beta + flags; 2: scal[kNorm] = sum; 3: CG init; 4: scal[kBB] = sum
+hipError_t launch_batch_scalar(int op, int nsys, const BatchSysTable& sys, double* scal, int* flags,
+                               const double* partial, int64_t pstride, double tol2, int max_iter, hipStream_t s);
 
 }  // namespace tmh

@@ -25,7 +25,7 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-HOP_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("hop.hip", "common.h", "kernels.h")]
+HOP_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("hop.hip", "hop_body.h", "common.h", "kernels.h")]
 DOMINANT = "tmh::hop_kernel<double, 0>"
 COPY = "stream_copy_kernel"
 

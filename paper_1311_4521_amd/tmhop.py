@@ -81,6 +81,16 @@ _sig("tmh_solve_full", _I, [_P, _P, _P, _P, _P, _P, _D, _D, _P, _D, _I, _I, ctyp
 _sig("tmh_scalar_prod_r", _I, [_P, ctypes.POINTER(_D), _P, _P, _I])
 _sig("tmh_norm2", _I, [_P, ctypes.POINTER(_D), _P, _I])
 _sig("tmh_stream_copy", _I, [_P, _P, _P, _S])
+class BatchMember(ctypes.Structure):
+    """Mirror of tmh_batch_member."""
+    _fields_ = [("lat", _P), ("nrhs", _I), ("x", _P), ("b", _P), ("gauge", _P), ("kappa", _D),
+                ("mu", _D), ("theta", _D * 4)]
+
+
+_sig("tmh_hop_apply_mrhs", _I, [_P, _I, _P, _P, _P, _I, _D, _P, _I, _I])
+_sig("tmh_batch_cg_solve", _I, [ctypes.POINTER(BatchMember), _I, _D, _I, _I, _I, ctypes.POINTER(_I),
+                                ctypes.POINTER(_D)])
+_sig("tmh_autotune_mrhs", _I, [_P, _P, _I, _I, ctypes.c_char_p, ctypes.POINTER(_I), ctypes.POINTER(_D)])
 _sig("tmh_profile_enable", _I, [_P, _I])
 _sig("tmh_profile_read", _I, [_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D)])
 _sig("tmh_status_string", ctypes.c_char_p, [_I])
@@ -88,7 +98,8 @@ _sig("tmh_status_string", ctypes.c_char_p, [_I])
 EXPORTED = ("tmh_lattice_create", "tmh_lattice_destroy", "tmh_lattice_set_stream",
             "tmh_half_volume", "tmh_site_stride", "tmh_spinor_bytes", "tmh_gauge_bytes",
             "tmh_gauge_import", "tmh_spinor_import", "tmh_spinor_export", "tmh_hop_apply",
-            "tmh_qtm_apply", "tmh_cg_solve", "tmh_hop_force", "tmh_qtm_force", "tmh_gauge_export", "tmh_solve_full",
+            "tmh_qtm_apply", "tmh_cg_solve", "tmh_hop_force", "tmh_qtm_force", "tmh_gauge_export", "tmh_solve_full", "tmh_hop_apply_mrhs",
+            "tmh_batch_cg_solve", "tmh_autotune_mrhs",
             "tmh_scalar_prod_r", "tmh_norm2",
             "tmh_stream_copy", "tmh_profile_enable", "tmh_profile_read", "tmh_status_string")
 
@@ -172,6 +183,12 @@ class Lattice:
         p = _PRECS[prec]
         f = torch.zeros if zero else torch.empty
         return f((12, self.S, 2), dtype=_DTYPE[p], device=self.device)
+
+    def new_spinors(self, nrhs, prec=F64, zero=True):
+        """nrhs internal spinors back to back: shape (nrhs, 12, S, 2)."""
+        p = _PRECS[prec]
+        f = torch.zeros if zero else torch.empty
+        return f((int(nrhs), 12, self.S, 2), dtype=_DTYPE[p], device=self.device)
 
     def new_gauge(self, prec=F64, zero=False):
         p = _PRECS[prec]
@@ -301,6 +318,79 @@ def solve_full(lat: Lattice, x_even, x_odd, b_even, b_odd, gauge, kappa, mu, the
     if st not in (TMH_OK, TMH_ERR_NOT_CONVERGED):
         raise TmhError(st, "tmh_solve_full")
     return it.value, res.value, st == TMH_OK
+
+
+SHAPES = {"256x1": 0, "128x2": 1, "64x4": 2, "128x4": 3, "64x12": 4}
+
+
+def _expect_multi(t, lat, prec, nrhs):
+    shape = (int(nrhs), 12, lat.S, 2)
+    if not torch.is_tensor(t) or t.device != lat.device or t.dtype != _DTYPE[prec] \
+            or tuple(t.shape) != shape or not t.is_contiguous():
+        raise ValueError(f"multi-RHS buffer must be a contiguous {_DTYPE[prec]} tensor of shape {shape}")
+
+
+def hop_apply_mrhs(lat: Lattice, direction, out, gauge, inp, kappa, theta, prec=F64, shape=-1):
+    """out[r] = H inp[r] for every right-hand side r in one launch."""
+    p = _PRECS[prec]
+    nrhs = inp.shape[0]
+    _expect_multi(out, lat, p, nrhs)
+    _expect_multi(inp, lat, p, nrhs)
+    _expect(gauge, lat, p, "gauge")
+    th, _keep = _theta(theta)
+    lat._sync_stream()
+    _check(_lib.tmh_hop_apply_mrhs(lat.handle, _DIRS[direction], out.data_ptr(), gauge.data_ptr(),
+                                   inp.data_ptr(), int(nrhs), float(kappa), th, p,
+                                   SHAPES.get(shape, shape)), "tmh_hop_apply_mrhs")
+    return out
+
+
+def batch_cg_solve(members, rel_tol=1e-10, max_iter=10000, shape=-1, use_graph=True):
+    """CG for every (member, rhs) system at once.  members: list of dicts with
+    keys lat, x, b, gauge, kappa, mu, theta (x, b: (nrhs, 12, S, 2) FP64).
+    Returns (iterations per system, true relative residual per system,
+    all converged)."""
+    arr = (BatchMember * len(members))()
+    nsys = 0
+    for k, m in enumerate(members):
+        lat = m["lat"]
+        nrhs = m["b"].shape[0]
+        _expect_multi(m["x"], lat, F64, nrhs)
+        _expect_multi(m["b"], lat, F64, nrhs)
+        _expect(m["gauge"], lat, F64, "gauge")
+        lat._sync_stream()
+        arr[k].lat = lat.handle
+        arr[k].nrhs = int(nrhs)
+        arr[k].x = m["x"].data_ptr()
+        arr[k].b = m["b"].data_ptr()
+        arr[k].gauge = m["gauge"].data_ptr()
+        arr[k].kappa = float(m["kappa"])
+        arr[k].mu = float(m["mu"])
+        for i, v in enumerate(m["theta"]):
+            arr[k].theta[i] = float(v)
+        nsys += int(nrhs)
+    it = (ctypes.c_int * nsys)()
+    res = (ctypes.c_double * nsys)()
+    st = _lib.tmh_batch_cg_solve(arr, len(members), float(rel_tol), int(max_iter),
+                                 SHAPES.get(shape, shape), 1 if use_graph else 0, it, res)
+    if st not in (TMH_OK, TMH_ERR_NOT_CONVERGED):
+        raise TmhError(st, "tmh_batch_cg_solve")
+    return list(it), list(res), st == TMH_OK
+
+
+def autotune_mrhs(lat: Lattice, gauge, nrhs, prec=F64, cache_path=None):
+    """Times every batch tile shape for nrhs right-hand sides on this lattice
+    (or reads the cache file) and keeps the fastest in the handle.  Returns
+    (shape index, microseconds per multi-RHS hop)."""
+    p = _PRECS[prec]
+    _expect(gauge, lat, p, "gauge")
+    sh = ctypes.c_int(-1)
+    us = ctypes.c_double(0.0)
+    lat._sync_stream()
+    _check(_lib.tmh_autotune_mrhs(lat.handle, gauge.data_ptr(), int(nrhs), p,
+                                  cache_path.encode() if cache_path else None, ctypes.byref(sh),
+                                  ctypes.byref(us)), "tmh_autotune_mrhs")
+    return sh.value, us.value
 
 
 FORCE_SU3, FORCE_EUCLID = 0, 1

@@ -1,0 +1,120 @@
+"""Batched path: the multi-right-hand-side hop of every tile shape against
+the oracle, the batched CG over several lattices (with and without graph
+replay) certified per system with the oracle's operator, and the autotuner."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1311_4521_amd as tm
+from helpers import THETA_AP, gauss, haar, mu_of, round_f32, site_rel_err
+
+pytestmark = pytest.mark.gpu
+
+TWIST = (0.5, 0.25, -0.3, 0.7)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def import_many(lat, fields, prec=tm.F64):
+    out = lat.new_spinors(len(fields), prec)
+    for r, f in enumerate(fields):
+        tm.spinor_import(lat, f, prec, out=out[r])
+    return out
+
+
+@pytest.mark.parametrize("prec", [tm.F64, tm.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("shape", list(tm.tmhop.SHAPES))
+@pytest.mark.parametrize("dims,nrhs", [((6, 8, 10, 4), 3), ((8, 8, 8, 8), 12), ((2, 2, 2, 2), 5)],
+                         ids=["6x8x10x4-3", "8x8x8x8-12", "2x2x2x2-5"])
+def test_hop_mrhs_matches_oracle(dims, nrhs, shape, prec):
+    kappa = 0.15
+    U = haar(dims, 501)
+    lat = tm.Lattice(dims)
+    G = tm.gauge_import(lat, U, prec)
+    psis = [gauss(lat.Vh, 510 + r) for r in range(nrhs)]
+    inp = import_many(lat, psis, prec)
+    out = lat.new_spinors(nrhs, prec)
+    tol = 1e-13 if prec == tm.F64 else 1e-5
+    for direction in ("eo", "oe"):
+        tm.hop_apply_mrhs(lat, direction, out, G, inp, kappa, TWIST, prec, shape)
+        for r in range(nrhs):
+            ref = oracle.hop(dims, direction, U, psis[r], kappa, TWIST)
+            got = host(tm.spinor_export(lat, out[r], prec))
+            assert site_rel_err(got, ref) <= tol, (direction, r)
+
+
+def batch_problem():
+    kappa, mu = 0.1632, mu_of(0.1632, 0.0013)
+    specs = [((8, 8, 8, 8), 3, 521), ((6, 8, 10, 4), 5, 531), ((4, 4, 4, 4), 2, 541)]
+    members, host_data = [], []
+    for dims, nrhs, seed in specs:
+        lat = tm.Lattice(dims)
+        U = haar(dims, seed)
+        bs = [gauss(lat.Vh, seed + 1 + r) for r in range(nrhs)]
+        members.append(dict(lat=lat, x=lat.new_spinors(nrhs), b=import_many(lat, bs),
+                            gauge=tm.gauge_import(lat, U), kappa=kappa, mu=mu, theta=THETA_AP))
+        host_data.append((dims, U, bs))
+    return members, host_data, kappa, mu
+
+
+@pytest.mark.parametrize("use_graph", [False, True], ids=["eager", "graph"])
+def test_batch_cg_certified(use_graph):
+    members, host_data, kappa, mu = batch_problem()
+    it, res, ok = tm.batch_cg_solve(members, 1e-10, 2000, -1, use_graph)
+    assert ok and len(it) == 10 and max(res) <= 1e-10
+    k = 0
+    for m, (dims, U, bs) in zip(members, host_data):
+        for r, b in enumerate(bs):
+            x = host(tm.spinor_export(m["lat"], m["x"][r]))
+            rr = b - oracle.normal(dims, U, x, kappa, mu, THETA_AP)
+            assert np.linalg.norm(rr) / np.linalg.norm(b) <= 1.05e-10, (dims, r)
+            # the same system solved alone
+            lat = m["lat"]
+            x1 = lat.new_spinor()
+            it1, res1, ok1 = tm.cg_solve(lat, x1, m["b"][r].contiguous(), m["gauge"], kappa, mu,
+                                         THETA_AP, 1e-10, 2000)
+            assert ok1 and abs(it1 - it[k]) <= 2
+            assert float((x1 - m["x"][r]).norm() / x1.norm()) < 1e-7
+            k += 1
+
+
+def test_batch_graph_replays_match_eager():
+    """Graph replay (several replays per solve, host work between them) gives
+    bitwise the same solutions and counts as eager launches."""
+    outs = []
+    for use_graph in (False, True, True):
+        members, _, _, _ = batch_problem()
+        it, res, ok = tm.batch_cg_solve(members, 1e-10, 2000, 2, use_graph)
+        assert ok
+        outs.append((it, res, [m["x"].clone() for m in members]))
+    for o in outs[1:]:
+        assert o[0] == outs[0][0] and o[1] == outs[0][1]
+        for a, b in zip(o[2], outs[0][2]):
+            assert torch.equal(a, b)
+
+
+def test_batch_not_converged_reported():
+    members, _, _, _ = batch_problem()
+    it, res, ok = tm.batch_cg_solve(members, 1e-10, 3, -1, True)
+    assert not ok and max(it) <= 3 * 4 and max(res) > 1e-10
+
+
+def test_autotune_and_cache(tmp_path):
+    dims = (8, 8, 8, 8)
+    lat = tm.Lattice(dims)
+    G = tm.gauge_import(lat, haar(dims, 551))
+    cache = str(tmp_path / "tune.txt")
+    sh, us = tm.autotune_mrhs(lat, G, 12, tm.F64, cache)
+    assert 0 <= sh < len(tm.tmhop.SHAPES) and us > 0
+    text = open(cache).read().split()
+    assert text[1] == "8x8x8x8" and text[2] == "f64" and text[3] == "12" and int(text[4]) == sh
+    lat2 = tm.Lattice(dims)
+    sh2, us2 = tm.autotune_mrhs(lat2, tm.gauge_import(lat2, haar(dims, 551)), 12, tm.F64, cache)
+    assert (sh2, us2) == (sh, float(text[5]))
+    assert len(open(cache).read().strip().splitlines()) == 1
