@@ -85,12 +85,181 @@ def cpu_baseline(dims, U, psi, kappa, theta, budget_s):
     }
 
 
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time_us(fn, reps=10, warm=2):
+    import torch
+    for _ in range(warm):
+        fn()
+    a, b = _events()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) * 1e3 / reps
+
+
+def run_batch(args):
+    """12 Gaussian right-hand sides on each of 16^3x32, 24^3x48 and 32^3x64
+    (Haar links): one batched CG (one launch per operator step for all 36
+    systems, HIP-graph replay, autotuned tile shape) against the 36 solves
+    one after another."""
+    import numpy as np
+    import torch
+
+    import fieldgen
+    import paper_1311_4521_amd as tm
+
+    torch.cuda.set_device(0)
+    kappa, mt, nrhs = 0.1632, 0.0013, 12
+    mu = mt / (2 * kappa)
+    theta = (1.0, 0.0, 0.0, 0.0)
+    seed = fieldgen.SEEDS["batch"]
+    members = []
+    for k, dims in enumerate([(64, 32, 32, 32), (48, 24, 24, 24), (32, 16, 16, 16)]):
+        log(f"batch member {dims}: generating links and {nrhs} sources")
+        lat = tm.Lattice(dims, 0)
+        G = tm.gauge_import(lat, fieldgen.gauge_haar(dims, seed + 10 * k))
+        B = lat.new_spinors(nrhs)
+        for r in range(nrhs):
+            tm.spinor_import(lat, fieldgen.spinor_gauss(lat.Vh, 1000 * (k + 1) + r), out=B[r])
+        members.append(dict(lat=lat, x=lat.new_spinors(nrhs), b=B, gauge=G, kappa=kappa, mu=mu,
+                            theta=theta))
+    big = members[0]
+    shape, tuned_us = tm.autotune_mrhs(big["lat"], big["gauge"], nrhs, tm.F64, args.tune_cache)
+    shape_name = [k for k, v in tm.tmhop.SHAPES.items() if v == shape][0]
+    log(f"autotuned tile shape {shape_name}: {tuned_us:.1f} us per 12-RHS hop at 32^3x64")
+    lat, G = big["lat"], big["gauge"]
+    Vh = lat.Vh
+    X1, Y1 = lat.new_spinor(), lat.new_spinor()
+    single_us = _time_us(lambda: tm.hop_apply(lat, "eo", Y1, G, X1, kappa, theta))
+    Xm, Ym = lat.new_spinors(nrhs), lat.new_spinors(nrhs)
+    multi_us = _time_us(lambda: tm.hop_apply_mrhs(lat, "eo", Ym, G, Xm, kappa, theta, tm.F64, shape))
+    del Xm, Ym
+    mrhs_bytes = (1152 + nrhs * 384) * Vh
+
+    def batched():
+        for m in members:
+            m["x"].zero_()
+        return tm.batch_cg_solve(members, 1e-10, 5000, shape, True)
+
+    it, res, ok = batched()
+    torch.cuda.synchronize()
+    tb = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        it, res, ok = batched()
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        if not ok:
+            raise SystemExit("batched CG did not converge")
+    log(f"batched: {1e3 * min(tb):.1f} ms for {sum(m['b'].shape[0] for m in members)} systems")
+    # the same systems one after another
+    seq_it = []
+    x = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for m in members:
+        x = m["lat"].new_spinor()
+        for r in range(nrhs):
+            x.zero_()
+            i1, r1, ok1 = tm.cg_solve(m["lat"], x, m["b"][r], m["gauge"], kappa, mu, theta, 1e-10, 5000)
+            seq_it.append(i1)
+            if not ok1:
+                raise SystemExit("sequential CG did not converge")
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    log(f"sequential: {1e3 * t_seq:.1f} ms")
+    t_batch = min(tb)
+    line = {
+        "metric": "batched CG time to 1e-10, 12 RHS on each of 16^3x32, 24^3x48, 32^3x64, "
+                  "vs the 36 solves one after another",
+        "value": round(1e3 * t_batch, 2), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(1e3 * t_batch, 2), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch: 3 Haar lattices x 12 Gaussian RHS, kappa=0.1632, "
+                               "2*kappa*mu=0.0013, antiperiodic time", "tile_shape": shape_name},
+        "sequential_ms": round(1e3 * t_seq, 2),
+        "speedup_vs_sequential": round(t_seq / t_batch, 3),
+        "iterations": {"batched_max": max(it), "sequential_max": max(seq_it)},
+        "max_true_rel_res": max(res),
+        "mrhs_hop_32x32x32x64": {"nrhs": nrhs, "us": round(multi_us, 1),
+                                 "us_per_rhs": round(multi_us / nrhs, 2),
+                                 "single_rhs_us": round(single_us, 1),
+                                 "speedup_per_rhs": round(single_us * nrhs / multi_us, 3),
+                                 "GBs_algorithmic": round(mrhs_bytes / (multi_us * 1e-6) / 1e9, 1),
+                                 "bytes_per_site": 1152 + nrhs * 384,
+                                 "GFlops": round(1320 * nrhs * Vh / (multi_us * 1e-6) / 1e9, 1)},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_adjoint(args):
+    """24^3x48 Haar links, Gaussian chi and psi: the su(3) force of
+    Re<chi, Qhat psi> (two hops + two force kernels) and one forward +
+    backward of the autograd function (psi and link gradients)."""
+    import numpy as np
+    import torch
+
+    import fieldgen
+    import paper_1311_4521_amd as tm
+    from paper_1311_4521_amd import autograd as tag
+
+    torch.cuda.set_device(0)
+    dims, kappa, mt = (48, 24, 24, 24), 0.1632, 0.0013
+    mu = mt / (2 * kappa)
+    theta = (1.0, 0.0, 0.0, 0.0)
+    seed = fieldgen.SEEDS["adjoint24"]
+    U = fieldgen.gauge_haar(dims, seed)
+    lat = tm.Lattice(dims, 0)
+    Vh = lat.Vh
+    chi = fieldgen.spinor_gauss(Vh, 100 + seed)
+    psi = fieldgen.spinor_gauss(Vh, 200 + seed)
+    G = tm.gauge_import(lat, U)
+    tc, tp = tm.spinor_import(lat, chi), tm.spinor_import(lat, psi)
+    F = lat.new_gauge(zero=True)
+    force_us = _time_us(lambda: tm.hop_force(lat, "eo", F, G, tc, tp, kappa, theta))
+    qforce_us = _time_us(lambda: tm.qtm_force(lat, F, G, tc, tp, kappa, mu, theta))
+    Ut = torch.from_numpy(U).cuda().requires_grad_()
+    pt = torch.from_numpy(psi).cuda().requires_grad_()
+    ct = torch.from_numpy(chi).cuda()
+
+    def fb():
+        Ut.grad = None
+        pt.grad = None
+        L = tag.qtm_bilinear(lat, ct, pt, Ut, kappa, mu, theta)
+        L.backward()
+
+    ag_us = _time_us(fb, reps=5, warm=1)
+    V = 2 * Vh
+    fbytes = 1920 * V
+    line = {
+        "metric": "gauge-link force of Re<chi, Qhat psi> at 24^3x48",
+        "value": round(qforce_us / 1e3, 4), "unit": "ms", "n_gpus": 1, "steps": 10, "warmup": 2,
+        "ms_per_step": round(qforce_us / 1e3, 4), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "adjoint: 24^3x48 Haar links, Gaussian chi and psi, kappa=0.1632, "
+                               "2*kappa*mu=0.0013"},
+        "hop_force_kernel": {"us": round(force_us, 1), "bytes_per_site": 1920,
+                             "GBs_algorithmic": round(fbytes / (force_us * 1e-6) / 1e9, 1),
+                             "frac_of_8TBs": round(fbytes / (force_us * 1e-6) / 8e12, 4)},
+        "qtm_force_us": round(qforce_us, 1),
+        "autograd_forward_backward_ms": round(ag_us / 1e3, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="qtm32", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="qtm32", choices=sorted(WORKLOADS) + ["batch", "adjoint24"])
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (batch workload)")
     ap.add_argument("--mixed-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -99,6 +268,11 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(see DESIGN.md for how the lattice would shard)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "adjoint24":
+        return run_adjoint(args)
 
     import numpy as np
     import torch
