@@ -333,8 +333,7 @@ def main():
     hop_us = ms0 * 1e3 / n0
     achieved = BYTES_PER_SITE_F64 * Vh / (hop_us * 1e-6) / 1e9
     per_kind = {}
-    names = ["f64_ainv_or_plain", "f64_twist", "f64_twist_norm", "f32_ainv_or_plain", "f32_twist",
-             "f32_twist_norm"]
+    names = tmhop.PROFILE_NAMES
     for k, (n, ms) in enumerate(counts):
         if n:
             per_kind[names[k]] = {"launches": n, "avg_us": round(ms * 1e3 / n, 2)}

@@ -250,10 +250,11 @@ tmh_status tmh_stream_copy(tmh_lattice* lat, void* dst, const void* src, size_t 
  * events on the handle's stream.  tmh_profile_enable(on) resets the totals.
  * tmh_profile_read waits for the recorded launches and returns, for one
  * kernel kind, the number of launches and their summed duration in ms since
- * the last reset.  Kinds: 3*prec + mode, where prec is TMH_F64 (0) or TMH_F32
+ * the last reset.  Kinds: 4*prec + mode, where prec is TMH_F64 (0) or TMH_F32
  * (1) and mode is 0 (plain hop, or hop with the A^-1 store), 1 (hop with the
- * gamma_5 [A in - .] epilogue), 2 (as 1, plus the fused norm). */
-#define TMH_PROFILE_KINDS 6
+ * gamma_5 [A in - .] epilogue), 2 (as 1, plus the fused norm), 3 (as 1, with
+ * the CG update r -= alpha q, x += alpha p and |r|^2 fused in). */
+#define TMH_PROFILE_KINDS 8
 tmh_status tmh_profile_enable(tmh_lattice* lat, int on);
 tmh_status tmh_profile_read(tmh_lattice* lat, int kind, long long* launches, double* total_ms);
 

@@ -154,7 +154,7 @@ hipError_t hop_launch(tmh_lattice* l, const HopArgs<R>& a, int mode) {
             return hipErrorUnknown;
         }
     }
-    e.kind = (sizeof(R) == 8 ? 0 : 3) + mode;
+    e.kind = (sizeof(R) == 8 ? 0 : 4) + mode;
     hipError_t err = hipEventRecord(e.start, l->stream);
     if (err == hipSuccess) err = tmh::launch_hop<R>(a, mode, l->stream);
     if (err == hipSuccess) err = hipEventRecord(e.stop, l->stream);
@@ -221,6 +221,40 @@ hipError_t force_launch(tmh_lattice* l, int pout, void* force, const void* gauge
     f.cx_re[1] = cd_re;
     f.cx_im[1] = cd_im;
     return tmh::launch_force(f, l->stream);
+}
+
+// The second operator of a CG iteration: q = Qhat(-) v, never stored; the
+// last launch applies r -= alpha q, x += alpha p (alpha from the device
+// scalars) and writes the |r|^2 partials.
+template <typename R>
+tmh_status qtm_update(tmh_lattice* l, void* x, void* r, const void* p, const void* gauge, const void* v, void* te,
+                      double kappa, double mu, const double theta[4], double* partial, const int* done) {
+    using W = typename tmh::Word<R>::T;
+    const double mt = -2.0 * kappa * mu;
+    const double D = 1.0 + mt * mt;
+    HopArgs<R> a = hop_args<R>(l, 0, te, gauge, v, theta);
+    a.done = done;
+    a.c_re[0] = (R)(kappa / D);
+    a.c_im[0] = (R)(-kappa * mt / D);
+    a.c_re[1] = (R)(kappa / D);
+    a.c_im[1] = (R)(kappa * mt / D);
+    TMH_TRY_HIP(hop_launch<R>(l, a, 0));
+    HopArgs<R> b = hop_args<R>(l, 1, nullptr, gauge, te, theta);
+    b.done = done;
+    b.aux = (const W*)v;
+    b.partial = partial;
+    b.xio = (W*)x;
+    b.rio = (W*)r;
+    b.pin = (const W*)p;
+    b.scal = l->scal;
+    b.c_re[0] = (R)(-kappa);
+    b.c_re[1] = (R)kappa;
+    b.d_re[0] = (R)1;
+    b.d_im[0] = (R)mt;
+    b.d_re[1] = (R)-1;
+    b.d_im[1] = (R)mt;
+    TMH_TRY_HIP(hop_launch<R>(l, b, 3));
+    return TMH_OK;
 }
 
 tmh_status check_lat(const tmh_lattice* l) { return l ? TMH_OK : TMH_ERR_ARG; }
@@ -291,10 +325,9 @@ tmh_status cg_recursion(tmh_lattice* l, void* x, void* r, void* p, void* v, void
             TMH_TRY(qtm_launch<R>(l, v, gauge, p, te, kappa, mu, theta, +1, l->partial, l->flags));
             TMH_TRY_HIP(tmh::launch_cg_alpha<R>(l->scal, l->partial, nb_hop, l->flags, l->stream));
             // q = Qhat(-) v = A p
-            TMH_TRY(qtm_launch<R>(l, q, gauge, v, te, kappa, mu, theta, -1, nullptr, l->flags));
-            TMH_TRY_HIP(tmh::launch_cg_xr<R>((W*)x, (W*)r, (const W*)p, (const W*)q, l->scal, l->partial, l->g,
-                                             l->flags, l->stream));
-            TMH_TRY_HIP(tmh::launch_cg_beta(l->scal, l->partial, nb_blas, l->flags, max_iter, l->stream));
+            // q = Qhat(-) v = A p, fused with x += alpha p, r -= alpha q and |r|^2
+            TMH_TRY(qtm_update<R>(l, x, r, p, gauge, v, te, kappa, mu, theta, l->partial, l->flags));
+            TMH_TRY_HIP(tmh::launch_cg_beta(l->scal, l->partial, nb_hop, l->flags, max_iter, l->stream));
             TMH_TRY_HIP(tmh::launch_cg_p<R>((W*)p, (const W*)r, l->scal, l->g, l->flags, l->stream));
         }
         TMH_TRY(read_scalars(l));

@@ -14,6 +14,9 @@
 //   MODE 0  out_s = c_{s/2} acc_s                      plain H, or A^-1 H
 //   MODE 1  out_s = c_{s/2} acc_s + d_{s/2} aux_s       gamma_5 [A aux - H (.)]
 //   MODE 2  as MODE 1, plus the per-workgroup partial of |out|^2 (FP64)
+//   MODE 3  CG update fused into the last hop of an iteration: with
+//           q = MODE 1 result (kept in registers), r -= alpha q, x += alpha p
+//           and the per-workgroup partial of |r|^2; q is not stored
 #include "common.h"
 #include "kernels.h"
 
@@ -42,6 +45,7 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> 
         const SiteNb n = site_neighbours(a.g, c, lex);
         hop_site<R, TMH_HOP_PIPE != 0>(acc, a, n, i);
         const int S = a.g.S;
+        const R alpha = MODE == 3 ? (R)a.scal[kAlpha] : (R)0;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const cx<R> cc = mk<R>(a.c_re[s >> 1], a.c_im[s >> 1]);
@@ -52,11 +56,22 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> 
                 if constexpr (MODE >= 1)
                     o += mk<R>(a.d_re[s >> 1], a.d_im[s >> 1]) * bload<R, out_aux<R>()>(a.aux + comp, S, i);
                 if constexpr (MODE == 2) nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
-                bstore<R, out_aux<R>()>(a.out + comp, S, i, o);
+                if constexpr (MODE == 3) {
+                    cx<R> r = bload<R>(a.rio + comp, S, i);
+                    cx<R> x = bload<R>(a.xio + comp, S, i);
+                    const cx<R> p = bload<R>(a.pin + comp, S, i);
+                    r -= alpha * o;
+                    x += alpha * p;
+                    bstore<R>(a.rio + comp, S, i, r);
+                    bstore<R>(a.xio + comp, S, i, x);
+                    nrm += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+                } else {
+                    bstore<R, out_aux<R>()>(a.out + comp, S, i, o);
+                }
             }
         }
     }
-    if constexpr (MODE == 2) {
+    if constexpr (MODE >= 2) {
         const double s = block_sum<kHopBlock>(nrm);
         if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
     }
@@ -71,7 +86,8 @@ hipError_t launch_hop(const HopArgs<R>& a, int mode, hipStream_t stream) {
     switch (mode) {
         case 0: hipLaunchKernelGGL((hop_kernel<R, 0>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
         case 1: hipLaunchKernelGGL((hop_kernel<R, 1>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
-        default: hipLaunchKernelGGL((hop_kernel<R, 2>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        case 2: hipLaunchKernelGGL((hop_kernel<R, 2>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        default: hipLaunchKernelGGL((hop_kernel<R, 3>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
     }
     return hipGetLastError();
 }

@@ -14,7 +14,11 @@ template <typename R> struct HopArgs {
     const typename Word<R>::T* gout;  // links U_mu(x) of the output parity
     const typename Word<R>::T* gin;   // links U_mu(y) of the input parity
     const typename Word<R>::T* aux;   // MODE >= 1: field added at the output site
-    double* partial;                  // MODE 2: per-workgroup |out|^2
+    double* partial;                  // MODE 2: per-workgroup |out|^2; MODE 3: |r|^2
+    typename Word<R>::T* xio;         // MODE 3: x += alpha p
+    typename Word<R>::T* rio;         // MODE 3: r -= alpha out (out itself is not stored)
+    const typename Word<R>::T* pin;   // MODE 3: p
+    const double* scal;               // MODE 3: alpha = scal[kAlpha]
     const int* done;                  // optional device flag: skip when set
     Geo g;
     int pout;                         // parity of the output sites

@@ -469,13 +469,16 @@ def stream_copy(lat: Lattice, dst, src):
     _check(_lib.tmh_stream_copy(lat.handle, dst.data_ptr(), src.data_ptr(), n), "tmh_stream_copy")
 
 
-PROFILE_KINDS = 6
+PROFILE_KINDS = 8
+PROFILE_NAMES = ["f64_ainv_or_plain", "f64_twist", "f64_twist_norm", "f64_twist_cg_update",
+                 "f32_ainv_or_plain", "f32_twist", "f32_twist_norm", "f32_twist_cg_update"]
 
 
 def profile_kind(prec, mode):
-    """Kernel kind index: 3*prec + mode (mode 0 plain/A^-1 store, 1 twist
-    epilogue, 2 twist epilogue with fused norm)."""
-    return 3 * _PRECS[prec] + int(mode)
+    """Kernel kind index: 4*prec + mode (mode 0 plain/A^-1 store, 1 twist
+    epilogue, 2 twist epilogue with fused norm, 3 twist epilogue with the
+    fused CG update)."""
+    return 4 * _PRECS[prec] + int(mode)
 
 
 def profile_enable(lat: Lattice, on=True):
