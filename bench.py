@@ -260,6 +260,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="qtm32", choices=sorted(WORKLOADS) + ["batch", "adjoint24"])
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (batch workload)")
+    ap.add_argument("--xgroup", type=int, default=None,
+                    help="fix the hop traversal x-group instead of autotuning it (profiling runs)")
     ap.add_argument("--mixed-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -299,7 +301,12 @@ def main():
     G = tm.gauge_import(lat, U)
     tb = tm.spinor_import(lat, b)
     x = lat.new_spinor()
-    log("fields resident on the device")
+    if args.xgroup is None:
+        xgroup, tuned_us = tm.autotune_hop(lat, G, tm.F64)
+        log(f"fields resident on the device; hop traversal x-group {xgroup} ({tuned_us:.1f} us, autotuned)")
+    else:
+        lat.traversal = xgroup = args.xgroup
+        log(f"fields resident on the device; hop traversal x-group {xgroup} (fixed)")
 
     def solve(inner):
         x.zero_()
@@ -390,7 +397,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w["label"], "dims_TXYZ": list(dims), "kappa": kappa,
-                   "two_kappa_mu": mt, "tol": 1e-10, "seed": w["seed"]},
+                   "two_kappa_mu": mt, "tol": 1e-10, "seed": w["seed"], "hop_traversal_xgroup": xgroup},
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),

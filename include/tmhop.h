@@ -96,6 +96,18 @@ tmh_status tmh_lattice_create(tmh_lattice** out, const int dims[4], int device, 
 void tmh_lattice_destroy(tmh_lattice* lat);
 tmh_status tmh_lattice_set_stream(tmh_lattice* lat, void* hip_stream);
 
+/* Traversal order of the hopping-matrix kernels.  Each XCD works through one
+ * contiguous range of time-slices; with xgroup > 0 it visits that range
+ * x-group by x-group (all its time-slices for xgroup consecutive x values,
+ * then the next group), which keeps the neighbours of the sites in flight
+ * within fewer L2 lines.  0 = even-odd order.  The default is the largest
+ * xgroup with xgroup * LY * LZ / 2 <= 8192 when the geometry tiles (LY*LZ/2 a
+ * multiple of 64, T a multiple of 8, xgroup divides LX); tmh_autotune_hop
+ * measures instead.  TMH_ERR_UNSUPPORTED if the geometry does not tile for
+ * this xgroup.  tmh_lattice_traversal returns the current value. */
+tmh_status tmh_lattice_set_traversal(tmh_lattice* lat, int xgroup);
+int tmh_lattice_traversal(const tmh_lattice* lat);
+
 /* Even-odd half volume Vh and the padded site stride S. */
 size_t tmh_half_volume(const tmh_lattice* lat);
 size_t tmh_site_stride(const tmh_lattice* lat);
@@ -185,6 +197,13 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* members, int nmembers, dou
  * and appended after timing.  Blocks. */
 tmh_status tmh_autotune_mrhs(tmh_lattice* lat, const void* gauge, int nrhs, tmh_prec prec,
                              const char* cache_path, int* best_shape, double* best_us);
+
+/* Autotuner of the hop traversal: times tmh_hop_apply for xgroup = 0 and
+ * every valid group on this lattice, keeps the fastest in the handle and
+ * returns it.  With cache_path, a line "<arch> <T>x<LX>x<LY>x<LZ> <f64|f32>
+ * hop <xgroup> <us>" is looked up first and appended after timing.  Blocks. */
+tmh_status tmh_autotune_hop(tmh_lattice* lat, const void* gauge, tmh_prec prec,
+                            const char* cache_path, int* best_xgroup, double* best_us);
 
 /* Full-lattice solve of M x = b, M = (1 + i mt gamma_5) - H the twisted-mass
  * Wilson operator on both checkerboards (what the inverter of the

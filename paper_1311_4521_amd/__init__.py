@@ -4,7 +4,8 @@ The computation lives in ``libtmhop.so`` (hand-written HIP for gfx950, C-ABI
 in ``include/tmhop.h``); ``tmhop`` is its ctypes binding.
 """
 
-from .tmhop import (EO, F32, F64, OE, Lattice, TmhError, autotune_mrhs, batch_cg_solve, cg_solve,
+from .tmhop import (EO, F32, F64, OE, Lattice, TmhError, autotune_hop, autotune_mrhs, batch_cg_solve,
+                    cg_solve,
                     gauge_export, gauge_import, hop_apply, hop_apply_mrhs, hop_force,
                     lattice_create, norm2, qtm_apply, qtm_force,
                     scalar_prod_r, solve_full, spinor_export, spinor_import, status_string)
@@ -12,5 +13,5 @@ from .tmhop import (EO, F32, F64, OE, Lattice, TmhError, autotune_mrhs, batch_cg
 __all__ = ["EO", "OE", "F64", "F32", "Lattice", "TmhError", "lattice_create", "gauge_import",
            "spinor_import", "spinor_export", "gauge_export", "hop_apply", "qtm_apply", "cg_solve",
            "hop_force", "qtm_force", "solve_full", "hop_apply_mrhs", "batch_cg_solve",
-           "autotune_mrhs",
+           "autotune_mrhs", "autotune_hop",
            "scalar_prod_r", "norm2", "status_string"]

@@ -35,6 +35,7 @@ struct tmh_lattice {
     void* mrhs[5];          // multi-RHS CG fields r, p, v, q (odd) and the even te, FP64
     int mrhs_cap;           // right-hand sides mrhs[] can hold
     int tuned[2][17];       // autotuned batch tile shape per (precision, nrhs <= 16), -1: none
+    int xgroup;             // hop traversal: x values per group (0: even-odd order)
     double2* v64[4];        // FP64 CG vectors r, p, v, q
     float2* v32[5];         // FP32 inner CG vectors r, p, v, q, d
     float2* gauge32;        // FP32 copy of the links for the mixed-precision inner solve
@@ -92,6 +93,26 @@ tmh_status ensure(void** p, size_t bytes) {
     return TMH_OK;
 }
 
+// The x-group traversal of the hop kernel applies when the geometry tiles
+// exactly: 64-site units fill whole (t, x) planes, every XCD owns whole
+// time-slices and a whole number of workgroups, and the group divides LX.
+bool xgroup_ok(const tmh_lattice* l, int xg) {
+    const int plane = l->dims[2] * l->dims[3] / 2;
+    return xg > 0 && plane % 64 == 0 && l->dims[0] % 8 == 0 && l->dims[1] % xg == 0 &&
+           l->g.Vh % (64 * 8) == 0 && (l->g.Vh / 64 / 8) % (tmh::kHopThreads / 64) == 0;
+}
+
+// Default: the largest group of x values whose sites (xg LY LZ / 2 per
+// time-slice) stay within 8192, i.e. about half the sites one XCD holds in
+// flight; 0 (even-odd order) when the geometry does not tile.
+int default_xgroup(const tmh_lattice* l) {
+    const int plane = l->dims[2] * l->dims[3] / 2;
+    int best = 0;
+    for (int xg = 1; xg <= l->dims[1]; ++xg)
+        if (xgroup_ok(l, xg) && (int64_t)xg * plane <= 8192) best = xg;
+    return best;
+}
+
 size_t spinor_bytes(const tmh_lattice* l, tmh_prec p) { return (size_t)12 * l->g.S * word_bytes(p); }
 size_t gauge_bytes(const tmh_lattice* l, tmh_prec p) { return (size_t)72 * l->g.S * word_bytes(p); }
 
@@ -114,6 +135,11 @@ HopArgs<R> hop_args(const tmh_lattice* l, int pout, void* out, const void* gauge
     a.gin = g + (int64_t)(1 - pout) * 36 * l->g.S;
     a.g = l->g;
     a.pout = pout;
+    if (xgroup_ok(l, l->xgroup)) {
+        a.xgroup = l->xgroup;
+        a.nyb = l->dims[2] * l->dims[3] / 2 / 64;
+        a.nt = l->dims[0] / 8;
+    }
     for (int m = 0; m < 4; ++m) {
         a.ph_re[m] = (R)cos(M_PI * theta[m]);
         a.ph_im[m] = (R)sin(M_PI * theta[m]);
@@ -455,6 +481,7 @@ tmh_status tmh_lattice_create(tmh_lattice** out, const int dims[4], int device, 
     l->g.S = (int)((V / 2 + 63) / 64 * 64);
     for (auto& row : l->tuned)
         for (int& v : row) v = -1;
+    l->xgroup = default_xgroup(l);
     const int nh = tmh::hop_blocks(l->g), nbl = tmh::blas_blocks(l->g);
     l->npartial = nh > nbl ? nh : nbl;
     tmh_status st = ensure((void**)&l->partial, sizeof(double) * l->npartial);
@@ -497,6 +524,16 @@ void tmh_lattice_destroy(tmh_lattice* l) {
     }
     delete l;
 }
+
+tmh_status tmh_lattice_set_traversal(tmh_lattice* l, int xgroup) {
+    TMH_TRY(check_lat(l));
+    if (xgroup < 0) return TMH_ERR_ARG;
+    if (xgroup > 0 && !xgroup_ok(l, xgroup)) return TMH_ERR_UNSUPPORTED;
+    l->xgroup = xgroup;
+    return TMH_OK;
+}
+
+int tmh_lattice_traversal(const tmh_lattice* l) { return l ? l->xgroup : -1; }
 
 tmh_status tmh_lattice_set_stream(tmh_lattice* l, void* hip_stream) {
     TMH_TRY(check_lat(l));
@@ -1160,6 +1197,97 @@ tmh_status tmh_autotune_mrhs(tmh_lattice* l, const void* gauge, int nrhs, tmh_pr
     if (cache_path) {
         if (FILE* f = fopen(cache_path, "a")) {
             fprintf(f, "%s %d %.3f\n", key, bs, best);
+            fclose(f);
+        }
+    }
+    return TMH_OK;
+}
+
+tmh_status tmh_autotune_hop(tmh_lattice* l, const void* gauge, tmh_prec prec, const char* cache_path, int* best_xgroup,
+                            double* best_us) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(prec));
+    if (!gauge || !best_xgroup || !best_us) return TMH_ERR_ARG;
+    DeviceGuard guard(l->device);
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, l->device) == hipSuccess) arch = prop.gcnArchName;
+    const size_t sp = arch.find(':');
+    if (sp != std::string::npos) arch = arch.substr(0, sp);
+    char key[256];
+    snprintf(key, sizeof key, "%s %dx%dx%dx%d %s hop", arch.c_str(), l->dims[0], l->dims[1], l->dims[2], l->dims[3],
+             prec == TMH_F64 ? "f64" : "f32");
+    if (cache_path) {
+        if (FILE* f = fopen(cache_path, "r")) {
+            char line[512];
+            int xg = -1;
+            double us = 0.0;
+            const size_t kl = strlen(key);
+            while (fgets(line, sizeof line, f)) {
+                int a = -1;
+                double b = 0.0;
+                if (strncmp(line, key, kl) == 0 && line[kl] == ' ' && sscanf(line + kl, " %d %lf", &a, &b) == 2 &&
+                    (a == 0 || xgroup_ok(l, a))) {
+                    xg = a;
+                    us = b;
+                }
+            }
+            fclose(f);
+            if (xg >= 0) {
+                l->xgroup = xg;
+                *best_xgroup = xg;
+                *best_us = us;
+                return TMH_OK;
+            }
+        }
+    }
+    void *in = nullptr, *out = nullptr;
+    const size_t sb = spinor_bytes(l, prec);
+    if (hipMalloc(&in, sb) != hipSuccess || hipMalloc(&out, sb) != hipSuccess) {
+        (void)hipFree(in);
+        return TMH_ERR_NOMEM;
+    }
+    tmh_status st = TMH_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const double theta[4] = {1.0, 0.0, 0.0, 0.0};
+    double best = 1e300;
+    int bx = 0;
+    const int saved = l->xgroup;
+    if (hipMemsetAsync(in, 0, sb, l->stream) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        st = TMH_ERR_HIP;
+    for (int xg = 0; xg <= l->dims[1] && st == TMH_OK; ++xg) {
+        if (xg > 0 && !xgroup_ok(l, xg)) continue;
+        l->xgroup = xg;
+        for (int w = 0; w < 2 && st == TMH_OK; ++w) st = tmh_hop_apply(l, TMH_EO, out, gauge, in, 0.1, theta, prec);
+        const int reps = 5;
+        if (st == TMH_OK && hipEventRecord(e0, l->stream) != hipSuccess) st = TMH_ERR_HIP;
+        for (int k = 0; k < reps && st == TMH_OK; ++k)
+            st = tmh_hop_apply(l, k % 2 ? TMH_OE : TMH_EO, out, gauge, in, 0.1, theta, prec);
+        float ms = 0.f;
+        if (st == TMH_OK && (hipEventRecord(e1, l->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = TMH_ERR_HIP;
+        if (st == TMH_OK && 1e3 * ms / reps < best) {
+            best = 1e3 * ms / reps;
+            bx = xg;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(l->stream);
+    (void)hipFree(in);
+    (void)hipFree(out);
+    if (st != TMH_OK) {
+        l->xgroup = saved;
+        return st;
+    }
+    l->xgroup = bx;
+    *best_xgroup = bx;
+    *best_us = best;
+    if (cache_path) {
+        if (FILE* f = fopen(cache_path, "a")) {
+            fprintf(f, "%s %d %.3f\n", key, bx, best);
             fclose(f);
         }
     }

@@ -24,15 +24,39 @@
 
 namespace tmh {
 
+// Traversal order.  Blocks are dealt round-robin to the 8 XCDs; the kernel
+// gives each XCD one contiguous range of the lattice instead (whole
+// time-slices when T is a multiple of 8), so that neighbouring sites share
+// that XCD's L2.  With xgroup > 0 the XCD's range is further visited in
+// 64-site units (one wave each) x-group by x-group: all the XCD's
+// time-slices for xgroup consecutive x values, then the next group.  The
+// sites resident at one time, and their neighbours, then form a more compact
+// region than in slice-by-slice order.  nyb units fill one (t, x) plane.
+// Returns the first site of the unit handled by wave w of hardware block b.
+__device__ __forceinline__ int unit_site(int b, int w, int nb, int xgroup, int nyb, int nt, int LX) {
+#if TMH_XCD_REMAP
+    const int q = nb / kXcds, r = nb % kXcds;
+    const int xc = b % kXcds, k = b / kXcds;
+    if (xgroup > 0) {
+        constexpr int W = kHopBlock / 64;
+        const int u = k * W + w;  // unit rank inside the XCD's range
+        const int per_group = nt * xgroup * nyb;
+        const int xg = u / per_group, rem = u - xg * per_group;
+        const int tl = rem / (xgroup * nyb), rem2 = rem - tl * (xgroup * nyb);
+        const int xi = rem2 / nyb, yb = rem2 - xi * nyb;
+        return (((xc * nt + tl) * LX + xg * xgroup + xi) * nyb + yb) * 64;
+    }
+    return (xc * q + (xc < r ? xc : r) + k) * kHopBlock + w * 64;
+#else
+    return b * kHopBlock + w * 64;
+#endif
+}
+
 template <typename R, int MODE>
 __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> a) {
     if (a.done && *a.done) return;
-#if TMH_XCD_REMAP
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-#else
-    const int blk = blockIdx.x;
-#endif
-    const int i = blk * kHopBlock + threadIdx.x;
+    const int i = unit_site(blockIdx.x, threadIdx.x >> 6, gridDim.x, a.xgroup, a.nyb, a.nt, a.g.L[1]) +
+                  (threadIdx.x & 63);
     double nrm = 0.0;
     if (i < a.g.Vh) {
         int c[4], lex;

@@ -56,6 +56,7 @@ namespace tmh {
 constexpr int kLinkAux = TMH_HOP_NT_LINKS ? 2 : 0;
 template <typename R> constexpr int out_aux() { return (TMH_HOP_NT_STORE && sizeof(R) == 8) ? 2 : 0; }
 constexpr int kHopBlock = TMH_HOP_BLOCK;
+static_assert(kHopBlock == kHopThreads, "the host sizes hop launches with kHopThreads");
 
 // Data one of the 8 terms needs: the neighbour's spinor and the link.
 template <typename R> struct TermData {

@@ -22,6 +22,7 @@ template <typename R> struct HopArgs {
     const int* done;                  // optional device flag: skip when set
     Geo g;
     int pout;                         // parity of the output sites
+    int xgroup, nyb, nt;              // traversal order (see hop.hip), xgroup = 0: eo order
     R ph_re[4], ph_im[4];             // exp(i pi theta_mu)
     R c_re[2], c_im[2];               // coefficient of the hopping sum, upper/lower spins
     R d_re[2], d_im[2];               // coefficient of aux, upper/lower spins
@@ -44,6 +45,7 @@ struct ForceArgs {
 hipError_t launch_force(const ForceArgs& a, hipStream_t s);
 
 int hop_blocks(const Geo& g);
+constexpr int kHopThreads = 256;  // workgroup size of hop_kernel (TMH_HOP_BLOCK)
 template <typename R> hipError_t launch_hop(const HopArgs<R>& a, int mode, hipStream_t s);
 
 // Layout conversion (layout.hip).

@@ -91,11 +91,15 @@ _sig("tmh_hop_apply_mrhs", _I, [_P, _I, _P, _P, _P, _I, _D, _P, _I, _I])
 _sig("tmh_batch_cg_solve", _I, [ctypes.POINTER(BatchMember), _I, _D, _I, _I, _I, ctypes.POINTER(_I),
                                 ctypes.POINTER(_D)])
 _sig("tmh_autotune_mrhs", _I, [_P, _P, _I, _I, ctypes.c_char_p, ctypes.POINTER(_I), ctypes.POINTER(_D)])
+_sig("tmh_lattice_set_traversal", _I, [_P, _I])
+_sig("tmh_lattice_traversal", _I, [_P])
+_sig("tmh_autotune_hop", _I, [_P, _P, _I, ctypes.c_char_p, ctypes.POINTER(_I), ctypes.POINTER(_D)])
 _sig("tmh_profile_enable", _I, [_P, _I])
 _sig("tmh_profile_read", _I, [_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D)])
 _sig("tmh_status_string", ctypes.c_char_p, [_I])
 
 EXPORTED = ("tmh_lattice_create", "tmh_lattice_destroy", "tmh_lattice_set_stream",
+            "tmh_lattice_set_traversal", "tmh_lattice_traversal", "tmh_autotune_hop",
             "tmh_half_volume", "tmh_site_stride", "tmh_spinor_bytes", "tmh_gauge_bytes",
             "tmh_gauge_import", "tmh_spinor_import", "tmh_spinor_export", "tmh_hop_apply",
             "tmh_qtm_apply", "tmh_cg_solve", "tmh_hop_force", "tmh_qtm_force", "tmh_gauge_export", "tmh_solve_full", "tmh_hop_apply_mrhs",
@@ -171,6 +175,15 @@ class Lattice:
 
     def _sync_stream(self):
         _lib.tmh_lattice_set_stream(self.handle, _P(_stream_ptr(self.device)))
+
+    @property
+    def traversal(self) -> int:
+        """x values per traversal group of the hop kernels (0: even-odd order)."""
+        return int(_lib.tmh_lattice_traversal(self.handle))
+
+    @traversal.setter
+    def traversal(self, xgroup):
+        _check(_lib.tmh_lattice_set_traversal(self.handle, int(xgroup)), "tmh_lattice_set_traversal")
 
     # -- buffers -------------------------------------------------------------
     def spinor_bytes(self, prec=F64) -> int:
@@ -376,6 +389,20 @@ def batch_cg_solve(members, rel_tol=1e-10, max_iter=10000, shape=-1, use_graph=T
     if st not in (TMH_OK, TMH_ERR_NOT_CONVERGED):
         raise TmhError(st, "tmh_batch_cg_solve")
     return list(it), list(res), st == TMH_OK
+
+
+def autotune_hop(lat: Lattice, gauge, prec=F64, cache_path=None):
+    """Times the hop traversal orders on this lattice (or reads the cache)
+    and keeps the fastest in the handle.  Returns (xgroup, microseconds)."""
+    p = _PRECS[prec]
+    _expect(gauge, lat, p, "gauge")
+    xg = ctypes.c_int(-1)
+    us = ctypes.c_double(0.0)
+    lat._sync_stream()
+    _check(_lib.tmh_autotune_hop(lat.handle, gauge.data_ptr(), p,
+                                 cache_path.encode() if cache_path else None, ctypes.byref(xg),
+                                 ctypes.byref(us)), "tmh_autotune_hop")
+    return xg.value, us.value
 
 
 def autotune_mrhs(lat: Lattice, gauge, nrhs, prec=F64, cache_path=None):

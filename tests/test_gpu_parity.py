@@ -311,3 +311,48 @@ def test_full_size_48x48x48x96_mixed_precision():
     xh = to_host(tm.spinor_export(lat, x))
     r = b - oracle.normal(dims, U, xh, kappa, mu, THETA_AP)
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.05e-10
+
+
+# ------------------------------------------------------------- traversal
+
+def test_traversal_orders_agree():
+    """Every valid traversal visits every site once: hop outputs are bitwise
+    equal across orders and match the oracle; CG converges in each."""
+    dims, kappa = (8, 8, 8, 16), 0.1632
+    mu = mu_of(kappa, 0.0013)
+    U = haar(dims, 601)
+    psi = gauss(int(np.prod(dims)) // 2, 602)
+    lat = tm.Lattice(dims)
+    G = tm.gauge_import(lat, U)
+    x = tm.spinor_import(lat, psi)
+    ref = {d: oracle.hop(dims, d, U, psi, kappa, THETA_AP) for d in ("eo", "oe")}
+    first = {}
+    with pytest.raises(tm.TmhError):
+        lat.traversal = 3          # does not divide LX
+    for xg in (0, 1, 2, 4, 8):
+        lat.traversal = xg
+        assert lat.traversal == xg
+        for d in ("eo", "oe"):
+            out = lat.new_spinor()
+            tm.hop_apply(lat, d, out, G, x, kappa, THETA_AP)
+            if d in first:
+                assert torch.equal(out, first[d]), (xg, d)
+            else:
+                first[d] = out
+                assert site_rel_err(to_host(tm.spinor_export(lat, out)), ref[d]) <= 1e-13
+        sol = lat.new_spinor()
+        it, res, ok = tm.cg_solve(lat, sol, x, G, kappa, mu, THETA_AP, 1e-10, 1000)
+        assert ok and res <= 1e-10
+
+
+def test_autotune_hop_cache(tmp_path):
+    dims = (8, 8, 8, 16)
+    lat = tm.Lattice(dims)
+    G = tm.gauge_import(lat, haar(dims, 611))
+    cache = str(tmp_path / "hop.txt")
+    xg, us = tm.autotune_hop(lat, G, tm.F64, cache)
+    assert xg in (0, 1, 2, 4, 8) and us > 0 and lat.traversal == xg
+    words = open(cache).read().split()
+    assert words[1:4] == ["8x8x8x16", "f64", "hop"] and int(words[4]) == xg
+    lat2 = tm.Lattice(dims)
+    assert tm.autotune_hop(lat2, tm.gauge_import(lat2, haar(dims, 611)), tm.F64, cache) == (xg, float(words[5]))
