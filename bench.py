@@ -11,9 +11,11 @@ value = Dslash GFlop/s over the timed steps: 1320 flop per output site per
 hopping-matrix application, times the applications the solves made, over the
 wall time of the steps.  The roofline entry is for the dominant kernel, the
 FP64 hopping matrix storing A^-1 H_eo p (1536 algorithmic bytes per site),
-timed live with HIP events on the stream it runs on.  The mixed-precision
-(FP32 inner) defect-correction solve of the same system is timed beside it,
-and the CPU oracle is timed on a bounded sample of the same workload.
+timed live with HIP events on the stream it runs on.  Beside it the same
+system is solved by the mixed-precision (FP32 inner) defect-correction CG,
+with 9-entry and with two-row FP32 links, and by FP64 CG on two-row FP64
+links (the third row of each SU(3) link rebuilt in the kernel); the CPU
+oracle is timed on a bounded sample of the same workload.
 """
 
 from __future__ import annotations
@@ -30,6 +32,7 @@ if ROOT not in sys.path:
 
 METRIC = "Dslash GFlop/s + % HBM roofline at 32^3x64; mixed vs FP64 CG time to 1e-10"
 FLOP_PER_SITE = 1320
+PREC_NAME = {0: "fp64", 1: "mixed fp32", 2: "fp64 two-row links", 3: "mixed fp32 two-row links"}
 BYTES_PER_SITE_F64 = 1536          # 8 links x 144 B + input spinor 192 B + output 192 B
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_f64_32x32x32x64_traffic.json")  # 32^3x64 only
@@ -363,24 +366,37 @@ def main():
     del src, dst
     log(f"streaming copy reference: {copy_gbs:.0f} GB/s ({2 * half} bytes moved per copy)")
 
-    # ---- mixed precision beside it
-    mixed = []
-    mixed_it = mixed_res = None
-    for k in range(1 + args.mixed_steps):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        it, res, ok = solve(tm.F32)
-        torch.cuda.synchronize()
-        if not ok:
-            raise SystemExit(f"mixed CG did not converge (residual {res})")
-        if k > 0:
-            mixed.append(time.perf_counter() - t1)
-        mixed_it, mixed_res = it, res
-    mixed_ms = 1e3 * (sum(mixed) / len(mixed)) if mixed else None
-    d = (x - x64).double()
-    mixed_vs_fp64 = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(x64))
+    # ---- the other solvers of the same system beside it: FP32-inner defect
+    # correction (9-entry and two-row FP32 links) and FP64 on two-row links
+    def time_solve(inner, reps):
+        times = []
+        for k in range(1 + reps):
+            tmhop.profile_enable(lat, True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            it, res, ok = solve(inner)
+            torch.cuda.synchronize()
+            if not ok:
+                raise SystemExit(f"CG ({PREC_NAME[inner]}) did not converge (residual {res})")
+            if k > 0:
+                times.append(time.perf_counter() - t1)
+        kinds = {}
+        for kk in range(tmhop.PROFILE_KINDS):
+            n, ms = tmhop.profile_read(lat, kk)
+            if n:
+                kinds[tmhop.PROFILE_NAMES[kk]] = {"launches": n, "avg_us": round(ms * 1e3 / n, 2)}
+        tmhop.profile_enable(lat, False)
+        d = (x - x64).double()
+        ms = 1e3 * sum(times) / len(times) if times else None
+        log(f"{PREC_NAME[inner]} solve: {ms} ms, {it} (inner) iterations, true residual {res:.3e}")
+        return {"ms": round(ms, 3) if ms else None, "iterations": it, "true_rel_res": res,
+                "rel_diff_vs_fp64_solution": float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(x64)),
+                "speedup_vs_fp64": round(fp64_ms / ms, 3) if ms else None, "kernels": kinds}
+
     fp64_ms = dt * 1e3 / args.steps
-    log(f"mixed solve: {mixed_ms} ms, {mixed_it} inner iterations")
+    mixed = time_solve(tm.F32, args.mixed_steps)
+    mixed_r12 = time_solve(tm.F32_R12, args.mixed_steps)
+    fp64_r12 = time_solve(tm.F64_R12, args.mixed_steps)
 
     traffic = measured_traffic(Vh)
     line = {
@@ -415,10 +431,9 @@ def main():
         "hop_gflops": round(FLOP_PER_SITE * Vh / (hop_us * 1e-6) / 1e9, 1),
         "kernels": per_kind,
         "cg_fp64": {"ms": round(fp64_ms, 3), "iterations": iters[0], "true_rel_res": res64},
-        "cg_mixed_f32": {"ms": round(mixed_ms, 3) if mixed_ms else None,
-                         "inner_iterations": mixed_it, "true_rel_res": mixed_res,
-                         "rel_diff_vs_fp64_solution": mixed_vs_fp64,
-                         "speedup_vs_fp64": round(fp64_ms / mixed_ms, 3) if mixed_ms else None},
+        "cg_mixed_f32": mixed,
+        "cg_mixed_f32_r12": mixed_r12,
+        "cg_fp64_r12": fp64_r12,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

@@ -40,12 +40,20 @@
  * Internal field layout ("site-coalesced structure of arrays").  S =
  * tmh_site_stride() is Vh = V/2 rounded up to a multiple of 64.  A complex
  * number is two reals (re, im) of the precision's real type: double for
- * TMH_F64, float for TMH_F32.
+ * TMH_F64 and TMH_F64_R12, float for TMH_F32 and TMH_F32_R12.
  *   spinor (one parity): component c = 3*spin + colour of site i is the
  *             complex element c*S + i; tmh_spinor_bytes() = 12*S complexes.
  *   gauge (whole lattice): element (a, b) of U_mu(x), x of parity p with
  *             even-odd index i, is the complex element ((p*4+mu)*9 + 3a+b)*S + i;
  *             tmh_gauge_bytes() = 72*S complexes.
+ *   gauge, two-row storage (TMH_F64_R12, TMH_F32_R12): only rows a = 0, 1 are
+ *             stored, element (a, b) at ((p*4+mu)*6 + 3a+b)*S + i,
+ *             tmh_gauge_bytes() = 48*S complexes.  The kernels rebuild row 2
+ *             as the complex conjugate of the cross product of rows 0 and 1,
+ *             which is exact for special unitary links (a unitary matrix with
+ *             determinant 1 equals the conjugate of its cofactor matrix), so
+ *             these formats represent SU(3) link fields only.  Spinors of an
+ *             _R12 precision are those of its base precision.
  * Elements i in [Vh, S) are padding: never read as data, never written by
  * the operators.
  *
@@ -83,7 +91,14 @@ typedef enum {
 
 typedef enum { TMH_EO = 0 /* odd -> even */, TMH_OE = 1 /* even -> odd */ } tmh_dir;
 
-typedef enum { TMH_F64 = 0, TMH_F32 = 1 } tmh_prec;
+/* Arithmetic and storage precision: spinor word and link storage (9 complex
+ * entries, or the two-row storage described above). */
+typedef enum {
+    TMH_F64 = 0,     /* FP64 spinors and links                      */
+    TMH_F32 = 1,     /* FP32 spinors and links                      */
+    TMH_F64_R12 = 2, /* FP64 spinors, FP64 links as their two rows  */
+    TMH_F32_R12 = 3  /* FP32 spinors, FP32 links as their two rows  */
+} tmh_prec;
 
 typedef struct tmh_lattice tmh_lattice;
 
@@ -117,8 +132,9 @@ size_t tmh_spinor_bytes(const tmh_lattice* lat, tmh_prec prec);
 size_t tmh_gauge_bytes(const tmh_lattice* lat, tmh_prec prec);
 
 /* Canonical FP64 -> internal layout in precision `prec` (rounded to nearest
- * for TMH_F32), and back.  src and dst are device buffers and must not
- * overlap (TMH_ERR_ALIAS). */
+ * for FP32), and back.  src and dst are device buffers and must not overlap
+ * (TMH_ERR_ALIAS).  Two-row gauge import keeps rows 0 and 1 of each link and
+ * export rebuilds row 2 from them. */
 tmh_status tmh_gauge_import(tmh_lattice* lat, void* dst, const double* src, tmh_prec prec);
 tmh_status tmh_spinor_import(tmh_lattice* lat, void* dst, const double* src, tmh_prec prec);
 tmh_status tmh_spinor_export(tmh_lattice* lat, double* dst, const void* src, tmh_prec prec);
@@ -148,6 +164,14 @@ tmh_status tmh_qtm_apply(tmh_lattice* lat, void* out, const void* gauge, const v
  *           residual, updates x and does every global reduction in FP64 on
  *           the device; each inner solve runs CG with the FP32 hopping matrix
  *           on an FP32 copy of the links made inside this call.
+ *   inner = TMH_F64_R12 / TMH_F32_R12: as TMH_F64 / TMH_F32, but the CG
+ *           recursion reads a two-row copy of the links (FP64 / FP32) made
+ *           inside this call, 1/3 fewer link bytes per hop, provided every
+ *           link's stored third row matches the conjugate cross product of
+ *           its first two to 1e-14 / 1e-7 (SU(3) links to rounding);
+ *           otherwise the 9-entry links are used.  True residuals always
+ *           use the caller's 9-entry FP64 links.
+ *   gauge is always the 9-entry FP64 field.
  * *iters receives the number of operator (Qhat^dagger Qhat) applications in
  * CG recursions (inner ones for mixed precision), *true_rel_res the final
  * |b - A x| / |b|.  TMH_ERR_NOT_CONVERGED if max_iter is reached.  Blocks. */
@@ -173,7 +197,8 @@ typedef struct {
 } tmh_batch_member;
 
 /* out_r = H in_r for r < nrhs (in/out: nrhs fields of precision prec back to
- * back), all in one launch; kappa folded in.  Enqueued on the stream. */
+ * back), all in one launch; kappa folded in.  Enqueued on the stream.
+ * TMH_F64 and TMH_F32 only (TMH_ERR_UNSUPPORTED for the _R12 codes). */
 tmh_status tmh_hop_apply_mrhs(tmh_lattice* lat, tmh_dir dir, void* out, const void* gauge,
                               const void* in, int nrhs, double kappa, const double theta[4],
                               tmh_prec prec, int shape);
@@ -194,14 +219,15 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* members, int nmembers, dou
  * this lattice for nrhs (<= 16) right-hand sides and keeps the fastest in the
  * handle (used by shape = -1).  With cache_path, a line
  * "<arch> <T>x<LX>x<LY>x<LZ> <f64|f32> <nrhs> <shape> <us>" is looked up first
- * and appended after timing.  Blocks. */
+ * and appended after timing.  TMH_F64 and TMH_F32 only.  Blocks. */
 tmh_status tmh_autotune_mrhs(tmh_lattice* lat, const void* gauge, int nrhs, tmh_prec prec,
                              const char* cache_path, int* best_shape, double* best_us);
 
 /* Autotuner of the hop traversal: times tmh_hop_apply for xgroup = 0 and
  * every valid group on this lattice, keeps the fastest in the handle and
- * returns it.  With cache_path, a line "<arch> <T>x<LX>x<LY>x<LZ> <f64|f32>
- * hop <xgroup> <us>" is looked up first and appended after timing.  Blocks. */
+ * returns it.  With cache_path, a line "<arch> <T>x<LX>x<LY>x<LZ> <prec> hop
+ * <xgroup> <us>" (prec one of f64, f32, f64r12, f32r12; gauge in that
+ * storage) is looked up first and appended after timing.  Blocks. */
 tmh_status tmh_autotune_hop(tmh_lattice* lat, const void* gauge, tmh_prec prec,
                             const char* cache_path, int* best_xgroup, double* best_us);
 
@@ -269,11 +295,12 @@ tmh_status tmh_stream_copy(tmh_lattice* lat, void* dst, const void* src, size_t 
  * events on the handle's stream.  tmh_profile_enable(on) resets the totals.
  * tmh_profile_read waits for the recorded launches and returns, for one
  * kernel kind, the number of launches and their summed duration in ms since
- * the last reset.  Kinds: 4*prec + mode, where prec is TMH_F64 (0) or TMH_F32
- * (1) and mode is 0 (plain hop, or hop with the A^-1 store), 1 (hop with the
- * gamma_5 [A in - .] epilogue), 2 (as 1, plus the fused norm), 3 (as 1, with
- * the CG update r -= alpha q, x += alpha p and |r|^2 fused in). */
-#define TMH_PROFILE_KINDS 8
+ * the last reset.  Kinds: 4*prec + mode, where prec is the tmh_prec code of
+ * the launch (0..3: spinor precision and the link storage it reads; the
+ * recursions of tmh_cg_solve report the copy they run on) and mode is 0 (plain hop, or hop with the A^-1 store), 1 (hop
+ * with the gamma_5 [A in - .] epilogue), 2 (as 1, plus the fused norm), 3 (as
+ * 1, with the CG update r -= alpha q, x += alpha p and |r|^2 fused in). */
+#define TMH_PROFILE_KINDS 16
 tmh_status tmh_profile_enable(tmh_lattice* lat, int on);
 tmh_status tmh_profile_read(tmh_lattice* lat, int kind, long long* launches, double* total_ms);
 

@@ -39,6 +39,7 @@ struct tmh_lattice {
     double2* v64[4];        // FP64 CG vectors r, p, v, q
     float2* v32[5];         // FP32 inner CG vectors r, p, v, q, d
     float2* gauge32;        // FP32 copy of the links for the mixed-precision inner solve
+    double2* gauge64r12;    // FP64 two-row copy of the links for the TMH_F64_R12 solve
     // launch timing (tmh_profile_*): event pairs around hopping-matrix launches
     struct EventPair {
         hipEvent_t start, stop;
@@ -76,7 +77,14 @@ struct DeviceGuard {
         if (st__ != TMH_OK) return st__; \
     } while (0)
 
-size_t word_bytes(tmh_prec p) { return p == TMH_F64 ? 16 : (p == TMH_F32 ? 8 : 0); }
+// A precision code is a spinor word (F64/F32) and a link storage format
+// (9 entries, or two rows for the _R12 codes); spinors of an _R12 code are
+// those of its base precision.
+bool prec_valid(tmh_prec p) { return p == TMH_F64 || p == TMH_F32 || p == TMH_F64_R12 || p == TMH_F32_R12; }
+tmh_prec base_prec(tmh_prec p) { return (p == TMH_F64 || p == TMH_F64_R12) ? TMH_F64 : TMH_F32; }
+int link_format(tmh_prec p) { return (p == TMH_F64_R12 || p == TMH_F32_R12) ? 1 : 0; }
+int link_comps(tmh_prec p) { return link_format(p) ? 6 : 9; }
+size_t word_bytes(tmh_prec p) { return prec_valid(p) ? (base_prec(p) == TMH_F64 ? 16 : 8) : 0; }
 
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
@@ -114,9 +122,12 @@ int default_xgroup(const tmh_lattice* l) {
 }
 
 size_t spinor_bytes(const tmh_lattice* l, tmh_prec p) { return (size_t)12 * l->g.S * word_bytes(p); }
-size_t gauge_bytes(const tmh_lattice* l, tmh_prec p) { return (size_t)72 * l->g.S * word_bytes(p); }
+size_t gauge_bytes(const tmh_lattice* l, tmh_prec p) {
+    return (size_t)8 * link_comps(p) * l->g.S * word_bytes(p);
+}
 
 tmh_status even_scratch(tmh_lattice* l, tmh_prec p, void** out) {
+    p = base_prec(p);
     TMH_TRY(ensure(&l->even[p], spinor_bytes(l, p)));
     *out = l->even[p];
     return TMH_OK;
@@ -124,17 +135,19 @@ tmh_status even_scratch(tmh_lattice* l, tmh_prec p, void** out) {
 
 template <typename R>
 HopArgs<R> hop_args(const tmh_lattice* l, int pout, void* out, const void* gauge, const void* in,
-                    const double theta[4]) {
+                    const double theta[4], int lf = 0) {
     using W = typename tmh::Word<R>::T;
     HopArgs<R> a;
     memset(&a, 0, sizeof a);
     a.out = (W*)out;
     a.in = (const W*)in;
     const W* g = (const W*)gauge;
-    a.gout = g + (int64_t)pout * 36 * l->g.S;
-    a.gin = g + (int64_t)(1 - pout) * 36 * l->g.S;
+    const int64_t per_parity = (int64_t)4 * (lf ? 6 : 9) * l->g.S;
+    a.gout = g + pout * per_parity;
+    a.gin = g + (1 - pout) * per_parity;
     a.g = l->g;
     a.pout = pout;
+    a.lf = lf;
     if (xgroup_ok(l, l->xgroup)) {
         a.xgroup = l->xgroup;
         a.nyb = l->dims[2] * l->dims[3] / 2 / 64;
@@ -180,7 +193,7 @@ hipError_t hop_launch(tmh_lattice* l, const HopArgs<R>& a, int mode) {
             return hipErrorUnknown;
         }
     }
-    e.kind = (sizeof(R) == 8 ? 0 : 4) + mode;
+    e.kind = 4 * ((sizeof(R) == 8 ? 0 : 1) + 2 * a.lf) + mode;
     hipError_t err = hipEventRecord(e.start, l->stream);
     if (err == hipSuccess) err = tmh::launch_hop<R>(a, mode, l->stream);
     if (err == hipSuccess) err = hipEventRecord(e.stop, l->stream);
@@ -196,10 +209,10 @@ hipError_t hop_launch(tmh_lattice* l, const HopArgs<R>& a, int mode) {
 // second launch also writes the |out|^2 partials.
 template <typename R>
 tmh_status qtm_launch(tmh_lattice* l, void* out, const void* gauge, const void* in, void* te, double kappa,
-                      double mu, const double theta[4], int sign, double* partial, const int* done) {
+                      double mu, const double theta[4], int sign, double* partial, const int* done, int lf = 0) {
     const double mt = 2.0 * kappa * mu * sign;
     const double D = 1.0 + mt * mt;
-    HopArgs<R> a = hop_args<R>(l, 0, te, gauge, in, theta);
+    HopArgs<R> a = hop_args<R>(l, 0, te, gauge, in, theta, lf);
     a.done = done;
     // A^-1 = (1 - i mt gamma_5)/D: upper spins (1 - i mt)/D, lower (1 + i mt)/D
     a.c_re[0] = (R)(kappa / D);
@@ -207,7 +220,7 @@ tmh_status qtm_launch(tmh_lattice* l, void* out, const void* gauge, const void* 
     a.c_re[1] = (R)(kappa / D);
     a.c_im[1] = (R)(kappa * mt / D);
     TMH_TRY_HIP(hop_launch<R>(l, a, 0));
-    HopArgs<R> b = hop_args<R>(l, 1, out, gauge, te, theta);
+    HopArgs<R> b = hop_args<R>(l, 1, out, gauge, te, theta, lf);
     b.done = done;
     b.aux = (const typename tmh::Word<R>::T*)in;
     b.partial = partial;
@@ -254,18 +267,19 @@ hipError_t force_launch(tmh_lattice* l, int pout, void* force, const void* gauge
 // scalars) and writes the |r|^2 partials.
 template <typename R>
 tmh_status qtm_update(tmh_lattice* l, void* x, void* r, const void* p, const void* gauge, const void* v, void* te,
-                      double kappa, double mu, const double theta[4], double* partial, const int* done) {
+                      double kappa, double mu, const double theta[4], double* partial, const int* done,
+                      int lf) {
     using W = typename tmh::Word<R>::T;
     const double mt = -2.0 * kappa * mu;
     const double D = 1.0 + mt * mt;
-    HopArgs<R> a = hop_args<R>(l, 0, te, gauge, v, theta);
+    HopArgs<R> a = hop_args<R>(l, 0, te, gauge, v, theta, lf);
     a.done = done;
     a.c_re[0] = (R)(kappa / D);
     a.c_im[0] = (R)(-kappa * mt / D);
     a.c_re[1] = (R)(kappa / D);
     a.c_im[1] = (R)(kappa * mt / D);
     TMH_TRY_HIP(hop_launch<R>(l, a, 0));
-    HopArgs<R> b = hop_args<R>(l, 1, nullptr, gauge, te, theta);
+    HopArgs<R> b = hop_args<R>(l, 1, nullptr, gauge, te, theta, lf);
     b.done = done;
     b.aux = (const W*)v;
     b.partial = partial;
@@ -285,7 +299,9 @@ tmh_status qtm_update(tmh_lattice* l, void* x, void* r, const void* p, const voi
 
 tmh_status check_lat(const tmh_lattice* l) { return l ? TMH_OK : TMH_ERR_ARG; }
 
-tmh_status check_prec(tmh_prec p) { return (p == TMH_F64 || p == TMH_F32) ? TMH_OK : TMH_ERR_UNSUPPORTED; }
+tmh_status check_prec(tmh_prec p) { return prec_valid(p) ? TMH_OK : TMH_ERR_UNSUPPORTED; }
+// Entry points that take full 9-entry links only.
+tmh_status check_prec_full(tmh_prec p) { return (p == TMH_F64 || p == TMH_F32) ? TMH_OK : TMH_ERR_UNSUPPORTED; }
 
 tmh_status check_theta(const double* theta) {
     if (!theta) return TMH_ERR_ARG;
@@ -336,7 +352,8 @@ constexpr int kChunk = 8;
 
 template <typename R>
 tmh_status cg_recursion(tmh_lattice* l, void* x, void* r, void* p, void* v, void* q, void* te, const void* gauge,
-                        double kappa, double mu, const double theta[4], double stop, int max_iter, int* iters) {
+                        double kappa, double mu, const double theta[4], double stop, int max_iter, int* iters,
+                        int lf = 0) {
     using W = typename tmh::Word<R>::T;
     const int nb_hop = tmh::hop_blocks(l->g), nb_blas = tmh::blas_blocks(l->g);
     // rr = |r|^2 into scal, flags reset
@@ -348,11 +365,10 @@ tmh_status cg_recursion(tmh_lattice* l, void* x, void* r, void* p, void* v, void
     for (;;) {
         for (int k = 0; k < kChunk; ++k) {
             // v = Qhat(+) p with |v|^2 = (p, A p)
-            TMH_TRY(qtm_launch<R>(l, v, gauge, p, te, kappa, mu, theta, +1, l->partial, l->flags));
+            TMH_TRY(qtm_launch<R>(l, v, gauge, p, te, kappa, mu, theta, +1, l->partial, l->flags, lf));
             TMH_TRY_HIP(tmh::launch_cg_alpha<R>(l->scal, l->partial, nb_hop, l->flags, l->stream));
-            // q = Qhat(-) v = A p
             // q = Qhat(-) v = A p, fused with x += alpha p, r -= alpha q and |r|^2
-            TMH_TRY(qtm_update<R>(l, x, r, p, gauge, v, te, kappa, mu, theta, l->partial, l->flags));
+            TMH_TRY(qtm_update<R>(l, x, r, p, gauge, v, te, kappa, mu, theta, l->partial, l->flags, lf));
             TMH_TRY_HIP(tmh::launch_cg_beta(l->scal, l->partial, nb_hop, l->flags, max_iter, l->stream));
             TMH_TRY_HIP(tmh::launch_cg_p<R>((W*)p, (const W*)r, l->scal, l->g, l->flags, l->stream));
         }
@@ -376,8 +392,56 @@ tmh_status alloc_cg32(tmh_lattice* l) {
     return even_scratch(l, TMH_F32, &te);
 }
 
+// Two-row copies of the links are used where every link's stored third row
+// matches the conjugate cross product of its first two to these bounds
+// (special unitary links): FP64 rounding of the entries for the FP64 solve,
+// FP32 rounding for the FP32 inner solve.  Otherwise all 9 entries are kept.
+constexpr double kR12Tol64 = 1e-14;
+constexpr double kR12Tol32 = 1e-7;
+
+// Largest deviation found by the last compress launch (waits).
+tmh_status link_deviation(tmh_lattice* l, double* dev) {
+    TMH_TRY_HIP(tmh::launch_reduce_max(l->scal + tmh::kNorm, l->partial, tmh::link_check_blocks(l->g), l->stream));
+    TMH_TRY(read_scalars(l));
+    *dev = l->h_scal[tmh::kNorm];
+    return TMH_OK;
+}
+
+// Links for the FP64 recursion: the caller's 9-entry field, or with r12 a
+// two-row copy when the links pass the check (*lf = 1).
+tmh_status links64(tmh_lattice* l, const void* gauge, bool r12, const void** used, int* lf) {
+    *used = gauge;
+    *lf = 0;
+    if (!r12) return TMH_OK;
+    TMH_TRY(ensure((void**)&l->gauge64r12, gauge_bytes(l, TMH_F64_R12)));
+    TMH_TRY_HIP(tmh::launch_compress_links<double>(l->gauge64r12, (const double2*)gauge, l->partial, l->g,
+                                                   l->stream));
+    double dev;
+    TMH_TRY(link_deviation(l, &dev));
+    if (dev <= kR12Tol64) {
+        *used = l->gauge64r12;
+        *lf = 1;
+    }
+    return TMH_OK;
+}
+
+// Narrows the FP64 links into l->gauge32: two rows with r12 when the links
+// pass the check (*lf = 1), else all 9 entries.
+tmh_status links32(tmh_lattice* l, const void* gauge, bool r12, int* lf) {
+    *lf = 0;
+    if (r12) {
+        TMH_TRY_HIP(tmh::launch_compress_links<float>(l->gauge32, (const double2*)gauge, l->partial, l->g,
+                                                      l->stream));
+        double dev;
+        TMH_TRY(link_deviation(l, &dev));
+        if (dev <= kR12Tol32) return *lf = 1, TMH_OK;
+    }
+    TMH_TRY_HIP(tmh::launch_narrow(l->gauge32, (const double2*)gauge, 72, l->g, l->stream));
+    return TMH_OK;
+}
+
 tmh_status cg_fp64(tmh_lattice* l, void* x, const void* b, const void* gauge, double kappa, double mu,
-                   const double theta[4], double tol, int max_iter, int* iters, double* res) {
+                   const double theta[4], double tol, int max_iter, int* iters, double* res, bool r12) {
     TMH_TRY(alloc_cg64(l));
     void *r = l->v64[0], *p = l->v64[1], *v = l->v64[2], *q = l->v64[3], *te = l->even[TMH_F64];
     double bb;
@@ -390,6 +454,9 @@ tmh_status cg_fp64(tmh_lattice* l, void* x, const void* b, const void* gauge, do
         return TMH_OK;
     }
     const double stop = tol * tol * bb;
+    const void* gr;
+    int lf;
+    TMH_TRY(links64(l, gauge, r12, &gr, &lf));
     double rr;
     TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
     int total = 0;
@@ -398,7 +465,7 @@ tmh_status cg_fp64(tmh_lattice* l, void* x, const void* b, const void* gauge, do
         if (*res <= tol) return *iters = total, TMH_OK;
         if (restart > 3 || total >= max_iter) break;
         int it = 0;
-        TMH_TRY(cg_recursion<double>(l, x, r, p, v, q, te, gauge, kappa, mu, theta, stop, max_iter - total, &it));
+        TMH_TRY(cg_recursion<double>(l, x, r, p, v, q, te, gr, kappa, mu, theta, stop, max_iter - total, &it, lf));
         total += it;
         TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
     }
@@ -409,15 +476,15 @@ tmh_status cg_fp64(tmh_lattice* l, void* x, const void* b, const void* gauge, do
 // Defect correction: FP64 true residual and solution update, FP32 inner CG.
 constexpr double kInnerTolMin = 1e-5;
 constexpr int kMaxOuter = 64;
-
 tmh_status cg_mixed(tmh_lattice* l, void* x, const void* b, const void* gauge, double kappa, double mu,
-                    const double theta[4], double tol, int max_iter, int* iters, double* res) {
+                    const double theta[4], double tol, int max_iter, int* iters, double* res, bool r12) {
     TMH_TRY(alloc_cg64(l));
     TMH_TRY(alloc_cg32(l));
     void *r = l->v64[0], *v = l->v64[2], *q = l->v64[3], *te = l->even[TMH_F64];
     float2 *r32 = l->v32[0], *p32 = l->v32[1], *v32 = l->v32[2], *q32 = l->v32[3], *d32 = l->v32[4];
     void* te32 = l->even[TMH_F32];
-    TMH_TRY_HIP(tmh::launch_narrow(l->gauge32, (const double2*)gauge, 72, l->g, l->stream));
+    int lf = 0;
+    TMH_TRY(links32(l, gauge, r12, &lf));
     double bb;
     TMH_TRY(reduce_dot<double>(l, &bb, b, b));
     *iters = 0;
@@ -442,7 +509,7 @@ tmh_status cg_mixed(tmh_lattice* l, void* x, const void* b, const void* gauge, d
         int it = 0;
         // |r32|^2 ~ rr; the stop test is relative to the narrowed residual
         TMH_TRY(cg_recursion<float>(l, d32, r32, p32, v32, q32, te32, l->gauge32, kappa, mu, theta,
-                                    inner * inner * rr, max_iter - total, &it));
+                                    inner * inner * rr, max_iter - total, &it, lf));
         total += it;
         TMH_TRY_HIP(tmh::launch_add_widen((double2*)x, d32, l->g, l->stream));
         TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
@@ -517,6 +584,7 @@ void tmh_lattice_destroy(tmh_lattice* l) {
     for (void* p : l->v64) (void)hipFree(p);
     for (void* p : l->v32) (void)hipFree(p);
     (void)hipFree(l->gauge32);
+    (void)hipFree(l->gauge64r12);
     (void)prof_flush(l);
     for (auto& e : l->prof_free) {
         (void)hipEventDestroy(e.start);
@@ -554,8 +622,12 @@ tmh_status tmh_gauge_import(tmh_lattice* l, void* dst, const double* src, tmh_pr
     DeviceGuard guard(l->device);
     if (prec == TMH_F64)
         TMH_TRY_HIP(tmh::launch_gauge_import<double>((double2*)dst, src, l->g, l->stream));
-    else
+    else if (prec == TMH_F32)
         TMH_TRY_HIP(tmh::launch_gauge_import<float>((float2*)dst, src, l->g, l->stream));
+    else if (prec == TMH_F64_R12)
+        TMH_TRY_HIP(tmh::launch_gauge_import_r12<double>((double2*)dst, src, l->g, l->stream));
+    else
+        TMH_TRY_HIP(tmh::launch_gauge_import_r12<float>((float2*)dst, src, l->g, l->stream));
     return TMH_OK;
 }
 
@@ -565,7 +637,7 @@ tmh_status tmh_spinor_import(tmh_lattice* l, void* dst, const double* src, tmh_p
     if (!dst || !src) return TMH_ERR_ARG;
     if (overlap(dst, spinor_bytes(l, prec), src, (size_t)l->g.Vh * 12 * 16)) return TMH_ERR_ALIAS;
     DeviceGuard guard(l->device);
-    if (prec == TMH_F64)
+    if (base_prec(prec) == TMH_F64)
         TMH_TRY_HIP(tmh::launch_spinor_import<double>((double2*)dst, src, l->g, l->stream));
     else
         TMH_TRY_HIP(tmh::launch_spinor_import<float>((float2*)dst, src, l->g, l->stream));
@@ -578,7 +650,7 @@ tmh_status tmh_spinor_export(tmh_lattice* l, double* dst, const void* src, tmh_p
     if (!dst || !src) return TMH_ERR_ARG;
     if (overlap(dst, (size_t)l->g.Vh * 12 * 16, src, spinor_bytes(l, prec))) return TMH_ERR_ALIAS;
     DeviceGuard guard(l->device);
-    if (prec == TMH_F64)
+    if (base_prec(prec) == TMH_F64)
         TMH_TRY_HIP(tmh::launch_spinor_export<double>(dst, (const double2*)src, l->g, l->stream));
     else
         TMH_TRY_HIP(tmh::launch_spinor_export<float>(dst, (const float2*)src, l->g, l->stream));
@@ -596,12 +668,13 @@ tmh_status tmh_hop_apply(tmh_lattice* l, tmh_dir dir, void* out, const void* gau
     if (overlap(out, sb, in, sb) || overlap(out, sb, gauge, gauge_bytes(l, prec))) return TMH_ERR_ALIAS;
     DeviceGuard guard(l->device);
     const int pout = dir == TMH_EO ? 0 : 1;
-    if (prec == TMH_F64) {
-        HopArgs<double> a = hop_args<double>(l, pout, out, gauge, in, theta);
+    const int lf = link_format(prec);
+    if (base_prec(prec) == TMH_F64) {
+        HopArgs<double> a = hop_args<double>(l, pout, out, gauge, in, theta, lf);
         a.c_re[0] = a.c_re[1] = kappa;
         TMH_TRY_HIP(hop_launch<double>(l, a, 0));
     } else {
-        HopArgs<float> a = hop_args<float>(l, pout, out, gauge, in, theta);
+        HopArgs<float> a = hop_args<float>(l, pout, out, gauge, in, theta, lf);
         a.c_re[0] = a.c_re[1] = (float)kappa;
         TMH_TRY_HIP(hop_launch<float>(l, a, 0));
     }
@@ -620,8 +693,10 @@ tmh_status tmh_qtm_apply(tmh_lattice* l, void* out, const void* gauge, const voi
     DeviceGuard guard(l->device);
     void* te;
     TMH_TRY(even_scratch(l, prec, &te));
-    if (prec == TMH_F64) return qtm_launch<double>(l, out, gauge, in, te, kappa, mu, theta, sign, nullptr, nullptr);
-    return qtm_launch<float>(l, out, gauge, in, te, kappa, mu, theta, sign, nullptr, nullptr);
+    const int lf = link_format(prec);
+    if (base_prec(prec) == TMH_F64)
+        return qtm_launch<double>(l, out, gauge, in, te, kappa, mu, theta, sign, nullptr, nullptr, lf);
+    return qtm_launch<float>(l, out, gauge, in, te, kappa, mu, theta, sign, nullptr, nullptr, lf);
 }
 
 tmh_status tmh_cg_solve(tmh_lattice* l, void* x, const void* b, const void* gauge, double kappa, double mu,
@@ -635,10 +710,10 @@ tmh_status tmh_cg_solve(tmh_lattice* l, void* x, const void* b, const void* gaug
     const size_t sb = spinor_bytes(l, TMH_F64);
     if (overlap(x, sb, b, sb) || overlap(x, sb, gauge, gauge_bytes(l, TMH_F64))) return TMH_ERR_ALIAS;
     DeviceGuard guard(l->device);
-    tmh_status st = inner == TMH_F64 ? cg_fp64(l, x, b, gauge, kappa, mu, theta, rel_tol, max_iter, iters,
-                                               true_rel_res)
-                                     : cg_mixed(l, x, b, gauge, kappa, mu, theta, rel_tol, max_iter, iters,
-                                                true_rel_res);
+    const bool r12 = link_format(inner) == 1;
+    tmh_status st = base_prec(inner) == TMH_F64
+                        ? cg_fp64(l, x, b, gauge, kappa, mu, theta, rel_tol, max_iter, iters, true_rel_res, r12)
+                        : cg_mixed(l, x, b, gauge, kappa, mu, theta, rel_tol, max_iter, iters, true_rel_res, r12);
     if (hipStreamSynchronize(l->stream) != hipSuccess) return TMH_ERR_HIP;
     return st;
 }
@@ -733,10 +808,12 @@ tmh_status tmh_solve_full(tmh_lattice* l, void* x_even, void* x_odd, const void*
     TMH_TRY(even_scratch(l, TMH_F64, &te));
     TMH_TRY(qtm_launch<double>(l, l->odd_rhs[1], gauge, l->odd_rhs[0], te, kappa, mu, theta, -1, nullptr,
                                nullptr));
-    tmh_status st = inner == TMH_F64 ? cg_fp64(l, x_odd, l->odd_rhs[1], gauge, kappa, mu, theta, rel_tol, max_iter,
-                                               iters, true_rel_res)
-                                     : cg_mixed(l, x_odd, l->odd_rhs[1], gauge, kappa, mu, theta, rel_tol,
-                                                max_iter, iters, true_rel_res);
+    const bool r12 = link_format(inner) == 1;
+    tmh_status st = base_prec(inner) == TMH_F64
+                        ? cg_fp64(l, x_odd, l->odd_rhs[1], gauge, kappa, mu, theta, rel_tol, max_iter, iters,
+                                  true_rel_res, r12)
+                        : cg_mixed(l, x_odd, l->odd_rhs[1], gauge, kappa, mu, theta, rel_tol, max_iter, iters,
+                                   true_rel_res, r12);
     if (st != TMH_OK && st != TMH_ERR_NOT_CONVERGED) return st;
     // x_e = A^-1 (b_e + H_eo x_o)
     HopArgs<double> b = hop_args<double>(l, 0, x_even, gauge, x_odd, theta);
@@ -856,7 +933,7 @@ extern "C" {
 tmh_status tmh_hop_apply_mrhs(tmh_lattice* l, tmh_dir dir, void* out, const void* gauge, const void* in, int nrhs,
                               double kappa, const double theta[4], tmh_prec prec, int shape) {
     TMH_TRY(check_lat(l));
-    TMH_TRY(check_prec(prec));
+    TMH_TRY(check_prec_full(prec));
     TMH_TRY(check_theta(theta));
     if (dir != TMH_EO && dir != TMH_OE) return TMH_ERR_ARG;
     if (!out || !gauge || !in || nrhs < 1 || !isfinite(kappa) || shape < -1 || shape >= tmh::kNumShapes)
@@ -1121,7 +1198,7 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* m, int nmem, double rel_to
 tmh_status tmh_autotune_mrhs(tmh_lattice* l, const void* gauge, int nrhs, tmh_prec prec, const char* cache_path,
                              int* best_shape, double* best_us) {
     TMH_TRY(check_lat(l));
-    TMH_TRY(check_prec(prec));
+    TMH_TRY(check_prec_full(prec));
     if (!gauge || nrhs < 1 || nrhs > 16 || !best_shape || !best_us) return TMH_ERR_ARG;
     DeviceGuard guard(l->device);
     hipDeviceProp_t prop;
@@ -1215,8 +1292,9 @@ tmh_status tmh_autotune_hop(tmh_lattice* l, const void* gauge, tmh_prec prec, co
     const size_t sp = arch.find(':');
     if (sp != std::string::npos) arch = arch.substr(0, sp);
     char key[256];
+    static const char* const kPrecName[4] = {"f64", "f32", "f64r12", "f32r12"};
     snprintf(key, sizeof key, "%s %dx%dx%dx%d %s hop", arch.c_str(), l->dims[0], l->dims[1], l->dims[2], l->dims[3],
-             prec == TMH_F64 ? "f64" : "f32");
+             kPrecName[prec]);
     if (cache_path) {
         if (FILE* f = fopen(cache_path, "r")) {
             char line[512];
@@ -1302,8 +1380,12 @@ tmh_status tmh_gauge_export(tmh_lattice* l, double* dst, const void* src, tmh_pr
     DeviceGuard guard(l->device);
     if (prec == TMH_F64)
         TMH_TRY_HIP(tmh::launch_gauge_export<double>(dst, (const double2*)src, l->g, l->stream));
-    else
+    else if (prec == TMH_F32)
         TMH_TRY_HIP(tmh::launch_gauge_export<float>(dst, (const float2*)src, l->g, l->stream));
+    else if (prec == TMH_F64_R12)
+        TMH_TRY_HIP(tmh::launch_gauge_export_r12<double>(dst, (const double2*)src, l->g, l->stream));
+    else
+        TMH_TRY_HIP(tmh::launch_gauge_export_r12<float>(dst, (const float2*)src, l->g, l->stream));
     return TMH_OK;
 }
 
@@ -1312,7 +1394,7 @@ tmh_status tmh_scalar_prod_r(tmh_lattice* l, double* result, const void* a, cons
     TMH_TRY(check_prec(prec));
     if (!result || !a || !b) return TMH_ERR_ARG;
     DeviceGuard guard(l->device);
-    return prec == TMH_F64 ? reduce_dot<double>(l, result, a, b) : reduce_dot<float>(l, result, a, b);
+    return base_prec(prec) == TMH_F64 ? reduce_dot<double>(l, result, a, b) : reduce_dot<float>(l, result, a, b);
 }
 
 tmh_status tmh_norm2(tmh_lattice* l, double* result, const void* a, tmh_prec prec) {

@@ -52,7 +52,7 @@ __device__ __forceinline__ int unit_site(int b, int w, int nb, int xgroup, int n
 #endif
 }
 
-template <typename R, int MODE>
+template <typename R, int MODE, int LF>
 __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> a) {
     if (a.done && *a.done) return;
     const int i = unit_site(blockIdx.x, threadIdx.x >> 6, gridDim.x, a.xgroup, a.nyb, a.nt, a.g.L[1]) +
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> 
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc[s][k] = mk<R>(0, 0);
         const SiteNb n = site_neighbours(a.g, c, lex);
-        hop_site<R, TMH_HOP_PIPE != 0>(acc, a, n, i);
+        hop_site<R, TMH_HOP_PIPE != 0, kLinkAux, LF>(acc, a, n, i);
         const int S = a.g.S;
         const R alpha = MODE == 3 ? (R)a.scal[kAlpha] : (R)0;
 #pragma unroll
@@ -103,17 +103,22 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> 
 
 int hop_blocks(const Geo& g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
 
+template <typename R, int LF>
+static hipError_t launch_hop_lf(const HopArgs<R>& a, int mode, int nb, hipStream_t stream) {
+    switch (mode) {
+        case 0: hipLaunchKernelGGL((hop_kernel<R, 0, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        case 1: hipLaunchKernelGGL((hop_kernel<R, 1, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        case 2: hipLaunchKernelGGL((hop_kernel<R, 2, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        default: hipLaunchKernelGGL((hop_kernel<R, 3, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+    }
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_hop(const HopArgs<R>& a, int mode, hipStream_t stream) {
     const int nb = hop_blocks(a.g);
     if (nb == 0) return hipSuccess;
-    switch (mode) {
-        case 0: hipLaunchKernelGGL((hop_kernel<R, 0>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
-        case 1: hipLaunchKernelGGL((hop_kernel<R, 1>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
-        case 2: hipLaunchKernelGGL((hop_kernel<R, 2>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
-        default: hipLaunchKernelGGL((hop_kernel<R, 3>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
-    }
-    return hipGetLastError();
+    return a.lf ? launch_hop_lf<R, 1>(a, mode, nb, stream) : launch_hop_lf<R, 0>(a, mode, nb, stream);
 }
 
 template hipError_t launch_hop<double>(const HopArgs<double>&, int, hipStream_t);

@@ -64,7 +64,22 @@ template <typename R> struct TermData {
     cx<R> u[3][3];
 };
 
-template <typename R, int LAUX>
+// Link storage: LF = 0 keeps all 9 entries; LF = 1 keeps the first two rows
+// (12 reals) and rebuilds the third as the complex conjugate of their cross
+// product, exact for special unitary links (det U = 1: U = conj(cofactors)).
+template <int LF> constexpr int link_comps() { return LF ? 6 : 9; }
+
+template <typename R>
+__device__ __forceinline__ void third_row(cx<R> (&u)[3][3]) {
+    const cx<R> c0 = u[0][1] * u[1][2] - u[0][2] * u[1][1];
+    const cx<R> c1 = u[0][2] * u[1][0] - u[0][0] * u[1][2];
+    const cx<R> c2 = u[0][0] * u[1][1] - u[0][1] * u[1][0];
+    u[2][0] = mk<R>(c0.re, -c0.im);
+    u[2][1] = mk<R>(c1.re, -c1.im);
+    u[2][2] = mk<R>(c2.re, -c2.im);
+}
+
+template <typename R, int LAUX, int LF>
 __device__ __forceinline__ void load_term(TermData<R>& d, const typename Word<R>::T* __restrict__ in,
                                           const typename Word<R>::T* __restrict__ link, int S, int jn, int jl) {
 #pragma unroll
@@ -72,7 +87,8 @@ __device__ __forceinline__ void load_term(TermData<R>& d, const typename Word<R>
 #pragma unroll
         for (int a = 0; a < 3; ++a) d.psi[s][a] = bload<R>(in + (int64_t)(3 * s + a) * S, S, jn);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) d.u[k / 3][k % 3] = bload<R, LAUX>(link + (int64_t)k * S, S, jl);
+    for (int k = 0; k < link_comps<LF>(); ++k) d.u[k / 3][k % 3] = bload<R, LAUX>(link + (int64_t)k * S, S, jl);
+    if constexpr (LF == 1) third_row<R>(d.u);
 }
 
 // One of the 8 terms: DIR = +1 adds (1 - gamma_mu) U_mu(x) psi(x+mu),
@@ -153,13 +169,14 @@ __device__ __forceinline__ SiteNb site_neighbours(const Geo& g, const int c[4], 
 // Term t = 2*mu + b: forward (b = 0) uses U_mu(x) from the output parity at
 // the site's own index i; backward (b = 1) uses U_mu(x - mu) from the input
 // parity at the neighbour's index.
-template <typename R, int T, int LAUX>
+template <typename R, int T, int LAUX, int LF>
 __device__ __forceinline__ void load_t(TermData<R>& d, const HopArgs<R>& a, const SiteNb& n, int i) {
     constexpr int MU = T / 2;
+    constexpr int NC = link_comps<LF>();
     if constexpr (T % 2 == 0)
-        load_term<R, LAUX>(d, a.in, a.gout + (int64_t)MU * 9 * a.g.S, a.g.S, n.jn[T], i);
+        load_term<R, LAUX, LF>(d, a.in, a.gout + (int64_t)MU * NC * a.g.S, a.g.S, n.jn[T], i);
     else
-        load_term<R, LAUX>(d, a.in, a.gin + (int64_t)MU * 9 * a.g.S, a.g.S, n.jn[T], n.jn[T]);
+        load_term<R, LAUX, LF>(d, a.in, a.gin + (int64_t)MU * NC * a.g.S, a.g.S, n.jn[T], n.jn[T]);
 }
 
 template <typename R, int T>
@@ -182,37 +199,37 @@ __device__ __forceinline__ void add_t(cx<R> (&acc)[4][3], const TermData<R>& d, 
 // Sum of the 8 terms.  PIPE loads term t+1 before computing term t (two
 // register sets); otherwise each term is loaded and consumed in turn.  LAUX
 // is the cache policy of the link loads.
-template <typename R, bool PIPE, int LAUX = kLinkAux>
+template <typename R, bool PIPE, int LAUX = kLinkAux, int LF = 0>
 __device__ __forceinline__ void hop_site(cx<R> (&acc)[4][3], const HopArgs<R>& a, const SiteNb& n, int i) {
     if constexpr (PIPE) {
     TermData<R> d0, d1;
-    load_t<R, 0, LAUX>(d0, a, n, i);
+    load_t<R, 0, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
-    load_t<R, 1, LAUX>(d1, a, n, i);
+    load_t<R, 1, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
     add_t<R, 0>(acc, d0, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 2, LAUX>(d0, a, n, i);
+    load_t<R, 2, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
     add_t<R, 1>(acc, d1, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 3, LAUX>(d1, a, n, i);
+    load_t<R, 3, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
     add_t<R, 2>(acc, d0, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 4, LAUX>(d0, a, n, i);
+    load_t<R, 4, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
     add_t<R, 3>(acc, d1, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 5, LAUX>(d1, a, n, i);
+    load_t<R, 5, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
     add_t<R, 4>(acc, d0, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 6, LAUX>(d0, a, n, i);
+    load_t<R, 6, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
     add_t<R, 5>(acc, d1, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 7, LAUX>(d1, a, n, i);
+    load_t<R, 7, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
     add_t<R, 6>(acc, d0, a, n);
     TMH_SCHED_FENCE();
@@ -220,7 +237,7 @@ __device__ __forceinline__ void hop_site(cx<R> (&acc)[4][3], const HopArgs<R>& a
     } else {
     TermData<R> d;
 #define TMH_TERM(T)              \
-    load_t<R, T, LAUX>(d, a, n, i);    \
+    load_t<R, T, LAUX, LF>(d, a, n, i);    \
     add_t<R, T>(acc, d, a, n);   \
     TMH_SCHED_FENCE();
     TMH_TERM(0) TMH_TERM(1) TMH_TERM(2) TMH_TERM(3) TMH_TERM(4) TMH_TERM(5) TMH_TERM(6) TMH_TERM(7)

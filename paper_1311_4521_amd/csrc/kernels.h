@@ -22,6 +22,7 @@ template <typename R> struct HopArgs {
     const int* done;                  // optional device flag: skip when set
     Geo g;
     int pout;                         // parity of the output sites
+    int lf;                           // link storage: 0 = 9 entries, 1 = two rows (12 reals)
     int xgroup, nyb, nt;              // traversal order (see hop.hip), xgroup = 0: eo order
     R ph_re[4], ph_im[4];             // exp(i pi theta_mu)
     R c_re[2], c_im[2];               // coefficient of the hopping sum, upper/lower spins
@@ -57,6 +58,19 @@ template <typename R>
 hipError_t launch_spinor_export(double* dst, const typename Word<R>::T* src, const Geo& g, hipStream_t s);
 template <typename R>
 hipError_t launch_gauge_export(double* dst, const typename Word<R>::T* src, const Geo& g, hipStream_t s);
+template <typename R>
+hipError_t launch_gauge_import_r12(typename Word<R>::T* dst, const double* src, const Geo& g, hipStream_t s);
+template <typename R>
+hipError_t launch_gauge_export_r12(double* dst, const typename Word<R>::T* src, const Geo& g, hipStream_t s);
+// Internal full FP64 links -> two-row links of type R, with the per-block
+// maximum of |conj(row0 x row1) - row2| over the links in partial[]
+// (link_check_blocks(g) entries, no more than hop_blocks(g)).
+template <typename R>
+hipError_t launch_compress_links(typename Word<R>::T* dst, const double2* src, double* partial, const Geo& g,
+                                 hipStream_t s);
+int link_check_blocks(const Geo& g);
+// out[0] = max(partial[0..n))
+hipError_t launch_reduce_max(double* out, const double* partial, int n, hipStream_t s);
 // Internal FP64 -> FP32 (spinor: ncomp = 12, gauge: ncomp = 72), and FP32 -> FP64.
 hipError_t launch_narrow(float2* dst, const double2* src, int ncomp, const Geo& g, hipStream_t s);
 hipError_t launch_widen(double2* dst, const float2* src, int ncomp, const Geo& g, hipStream_t s);

@@ -41,10 +41,14 @@ TMH_ERR_NOT_CONVERGED = -6
 TMH_ERR_UNSUPPORTED = -7
 
 EO, OE = 0, 1
-F64, F32 = 0, 1
+# precision codes: spinor word and link storage (F64_R12 / F32_R12 keep each
+# link as its first two rows, the third rebuilt in the kernels; SU(3) only)
+F64, F32, F64_R12, F32_R12 = 0, 1, 2, 3
 _DIRS = {"eo": EO, "oe": OE, EO: EO, OE: OE}
-_PRECS = {"f64": F64, "f32": F32, F64: F64, F32: F32}
-_DTYPE = {F64: torch.float64, F32: torch.float32}
+_PRECS = {"f64": F64, "f32": F32, "f64r12": F64_R12, "f32r12": F32_R12,
+          F64: F64, F32: F32, F64_R12: F64_R12, F32_R12: F32_R12}
+_DTYPE = {F64: torch.float64, F32: torch.float32, F64_R12: torch.float64, F32_R12: torch.float32}
+_LINK_COMPS = {F64: 9, F32: 9, F64_R12: 6, F32_R12: 6}
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -206,7 +210,7 @@ class Lattice:
     def new_gauge(self, prec=F64, zero=False):
         p = _PRECS[prec]
         f = torch.zeros if zero else torch.empty
-        return f((2, 4, 9, self.S, 2), dtype=_DTYPE[p], device=self.device)
+        return f((2, 4, _LINK_COMPS[p], self.S, 2), dtype=_DTYPE[p], device=self.device)
 
 
 def _complex_dev(x, shape, device):
@@ -219,7 +223,7 @@ def _complex_dev(x, shape, device):
 
 
 def _expect(t, lat, prec, kind):
-    shape = (12, lat.S, 2) if kind == "spinor" else (2, 4, 9, lat.S, 2)
+    shape = (12, lat.S, 2) if kind == "spinor" else (2, 4, _LINK_COMPS[prec], lat.S, 2)
     if not torch.is_tensor(t) or t.device != lat.device or t.dtype != _DTYPE[prec] \
             or tuple(t.shape) != shape or not t.is_contiguous():
         raise ValueError(f"{kind} buffer must be a contiguous {_DTYPE[prec]} tensor of shape "
@@ -496,9 +500,9 @@ def stream_copy(lat: Lattice, dst, src):
     _check(_lib.tmh_stream_copy(lat.handle, dst.data_ptr(), src.data_ptr(), n), "tmh_stream_copy")
 
 
-PROFILE_KINDS = 8
-PROFILE_NAMES = ["f64_ainv_or_plain", "f64_twist", "f64_twist_norm", "f64_twist_cg_update",
-                 "f32_ainv_or_plain", "f32_twist", "f32_twist_norm", "f32_twist_cg_update"]
+PROFILE_KINDS = 16
+PROFILE_NAMES = [f"{p}_{m}" for p in ("f64", "f32", "f64r12", "f32r12")
+                 for m in ("ainv_or_plain", "twist", "twist_norm", "twist_cg_update")]
 
 
 def profile_kind(prec, mode):

@@ -38,7 +38,8 @@ def test_solve_full_dense_2x2x2x2():
     assert np.linalg.norm(x.ravel() - xr) / np.linalg.norm(xr) < 1e-9
 
 
-@pytest.mark.parametrize("inner", [tm.F64, tm.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("inner", [tm.F64, tm.F32, tm.F64_R12, tm.F32_R12],
+                         ids=["f64", "f32", "f64r12", "f32r12"])
 @pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 8, 10, 4)], ids=lambda d: "x".join(map(str, d)))
 def test_solve_full_residual(dims, inner):
     kappa, mu = 0.1632, mu_of(0.1632, 0.0013)
