@@ -13,9 +13,10 @@ wall time of the steps.  The roofline entry is for the dominant kernel, the
 FP64 hopping matrix storing A^-1 H_eo p (1536 algorithmic bytes per site),
 timed live with HIP events on the stream it runs on.  Beside it the same
 system is solved by the mixed-precision (FP32 inner) defect-correction CG,
-with 9-entry and with two-row FP32 links, and by FP64 CG on two-row FP64
-links (the third row of each SU(3) link rebuilt in the kernel); the CPU
-oracle is timed on a bounded sample of the same workload.
+with 9-entry and with two-row FP32 links, by the same with FP16 storage in
+the inner solve, and by FP64 CG on two-row FP64 links (the third row of each
+SU(3) link rebuilt in the kernel); the CPU oracle is timed on a bounded
+sample of the same workload.
 """
 
 from __future__ import annotations
@@ -32,7 +33,8 @@ if ROOT not in sys.path:
 
 METRIC = "Dslash GFlop/s + % HBM roofline at 32^3x64; mixed vs FP64 CG time to 1e-10"
 FLOP_PER_SITE = 1320
-PREC_NAME = {0: "fp64", 1: "mixed fp32", 2: "fp64 two-row links", 3: "mixed fp32 two-row links"}
+PREC_NAME = {0: "fp64", 1: "mixed fp32", 2: "fp64 two-row links", 3: "mixed fp32 two-row links",
+             4: "mixed fp16 storage", 5: "mixed fp16 storage two-row links"}
 BYTES_PER_SITE_F64 = 1536          # 8 links x 144 B + input spinor 192 B + output 192 B
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_f64_32x32x32x64_traffic.json")  # 32^3x64 only
@@ -397,6 +399,8 @@ def main():
     mixed = time_solve(tm.F32, args.mixed_steps)
     mixed_r12 = time_solve(tm.F32_R12, args.mixed_steps)
     fp64_r12 = time_solve(tm.F64_R12, args.mixed_steps)
+    mixed_f16 = time_solve(tm.F16, args.mixed_steps)
+    mixed_f16_r12 = time_solve(tm.F16_R12, args.mixed_steps)
 
     traffic = measured_traffic(Vh)
     line = {
@@ -434,6 +438,8 @@ def main():
         "cg_mixed_f32": mixed,
         "cg_mixed_f32_r12": mixed_r12,
         "cg_fp64_r12": fp64_r12,
+        "cg_mixed_f16": mixed_f16,
+        "cg_mixed_f16_r12": mixed_f16_r12,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

@@ -39,8 +39,10 @@
  *
  * Internal field layout ("site-coalesced structure of arrays").  S =
  * tmh_site_stride() is Vh = V/2 rounded up to a multiple of 64.  A complex
- * number is two reals (re, im) of the precision's real type: double for
- * TMH_F64 and TMH_F64_R12, float for TMH_F32 and TMH_F32_R12.
+ * number is two reals (re, im) of the precision's storage type: double for
+ * TMH_F64 and TMH_F64_R12, float for TMH_F32 and TMH_F32_R12, IEEE binary16
+ * for TMH_F16 and TMH_F16_R12 (whose arithmetic is FP32).  Import rounds
+ * FP64 values once, to nearest even, into the storage type.
  *   spinor (one parity): component c = 3*spin + colour of site i is the
  *             complex element c*S + i; tmh_spinor_bytes() = 12*S complexes.
  *   gauge (whole lattice): element (a, b) of U_mu(x), x of parity p with
@@ -97,7 +99,9 @@ typedef enum {
     TMH_F64 = 0,     /* FP64 spinors and links                      */
     TMH_F32 = 1,     /* FP32 spinors and links                      */
     TMH_F64_R12 = 2, /* FP64 spinors, FP64 links as their two rows  */
-    TMH_F32_R12 = 3  /* FP32 spinors, FP32 links as their two rows  */
+    TMH_F32_R12 = 3, /* FP32 spinors, FP32 links as their two rows  */
+    TMH_F16 = 4,     /* FP16 storage, FP32 arithmetic               */
+    TMH_F16_R12 = 5  /* FP16 storage, links as their two rows       */
 } tmh_prec;
 
 typedef struct tmh_lattice tmh_lattice;
@@ -164,11 +168,17 @@ tmh_status tmh_qtm_apply(tmh_lattice* lat, void* out, const void* gauge, const v
  *           residual, updates x and does every global reduction in FP64 on
  *           the device; each inner solve runs CG with the FP32 hopping matrix
  *           on an FP32 copy of the links made inside this call.
- *   inner = TMH_F64_R12 / TMH_F32_R12: as TMH_F64 / TMH_F32, but the CG
- *           recursion reads a two-row copy of the links (FP64 / FP32) made
- *           inside this call, 1/3 fewer link bytes per hop, provided every
- *           link's stored third row matches the conjugate cross product of
- *           its first two to 1e-14 / 1e-7 (SU(3) links to rounding);
+ *   inner = TMH_F16: defect correction as TMH_F32, with every field of
+ *           the inner CG stored in FP16 (arithmetic and reductions in FP32 /
+ *           FP64).  Each inner solve takes the residual scaled to unit mean
+ *           square per real component, so that its vectors stay in FP16's
+ *           normal range, and stops at a relative residual no smaller than
+ *           3e-3; more outer steps replace the precision FP16 lacks.
+ *   inner = TMH_F64_R12 / TMH_F32_R12 / TMH_F16_R12: as without _R12, but
+ *           the CG recursion reads a two-row copy of the links made inside
+ *           this call, 1/3 fewer link bytes per hop, provided every link's
+ *           stored third row matches the conjugate cross product of its
+ *           first two to 1e-14 / 1e-7 / 1e-4 (SU(3) links to rounding);
  *           otherwise the 9-entry links are used.  True residuals always
  *           use the caller's 9-entry FP64 links.
  *   gauge is always the 9-entry FP64 field.
@@ -226,8 +236,8 @@ tmh_status tmh_autotune_mrhs(tmh_lattice* lat, const void* gauge, int nrhs, tmh_
 /* Autotuner of the hop traversal: times tmh_hop_apply for xgroup = 0 and
  * every valid group on this lattice, keeps the fastest in the handle and
  * returns it.  With cache_path, a line "<arch> <T>x<LX>x<LY>x<LZ> <prec> hop
- * <xgroup> <us>" (prec one of f64, f32, f64r12, f32r12; gauge in that
- * storage) is looked up first and appended after timing.  Blocks. */
+ * <xgroup> <us>" (prec one of f64, f32, f64r12, f32r12, f16, f16r12; gauge
+ * in that storage) is looked up first and appended after timing.  Blocks. */
 tmh_status tmh_autotune_hop(tmh_lattice* lat, const void* gauge, tmh_prec prec,
                             const char* cache_path, int* best_xgroup, double* best_us);
 
@@ -296,11 +306,11 @@ tmh_status tmh_stream_copy(tmh_lattice* lat, void* dst, const void* src, size_t 
  * tmh_profile_read waits for the recorded launches and returns, for one
  * kernel kind, the number of launches and their summed duration in ms since
  * the last reset.  Kinds: 4*prec + mode, where prec is the tmh_prec code of
- * the launch (0..3: spinor precision and the link storage it reads; the
+ * the launch (0..5: spinor precision and the link storage it reads; the
  * recursions of tmh_cg_solve report the copy they run on) and mode is 0 (plain hop, or hop with the A^-1 store), 1 (hop
  * with the gamma_5 [A in - .] epilogue), 2 (as 1, plus the fused norm), 3 (as
  * 1, with the CG update r -= alpha q, x += alpha p and |r|^2 fused in). */
-#define TMH_PROFILE_KINDS 16
+#define TMH_PROFILE_KINDS 24
 tmh_status tmh_profile_enable(tmh_lattice* lat, int on);
 tmh_status tmh_profile_read(tmh_lattice* lat, int kind, long long* launches, double* total_ms);
 

@@ -29,7 +29,7 @@ struct tmh_lattice {
     int* flags;             // {done, iterations}
     double* h_scal;         // pinned host mirror of scal
     int* h_flags;           // pinned host mirror of flags
-    void* even[2];          // intermediate even field per precision (Qtm)
+    void* even[3];          // intermediate even field per base precision (Qtm), prec_slot order
     void* even2;            // second FP64 even field (force chain, full solve)
     void* odd_rhs[2];       // FP64 odd fields of the full-lattice solve
     void* mrhs[5];          // multi-RHS CG fields r, p, v, q (odd) and the even te, FP64
@@ -37,8 +37,8 @@ struct tmh_lattice {
     int tuned[2][17];       // autotuned batch tile shape per (precision, nrhs <= 16), -1: none
     int xgroup;             // hop traversal: x values per group (0: even-odd order)
     double2* v64[4];        // FP64 CG vectors r, p, v, q
-    float2* v32[5];         // FP32 inner CG vectors r, p, v, q, d
-    float2* gauge32;        // FP32 copy of the links for the mixed-precision inner solve
+    void* vlow[2][5];       // inner CG vectors r, p, v, q, d of the mixed solve: [0] FP32, [1] FP16
+    void* glow[2];          // FP32 / FP16 copy of the links for the mixed-precision inner solve
     double2* gauge64r12;    // FP64 two-row copy of the links for the TMH_F64_R12 solve
     // launch timing (tmh_profile_*): event pairs around hopping-matrix launches
     struct EventPair {
@@ -77,14 +77,39 @@ struct DeviceGuard {
         if (st__ != TMH_OK) return st__; \
     } while (0)
 
-// A precision code is a spinor word (F64/F32) and a link storage format
-// (9 entries, or two rows for the _R12 codes); spinors of an _R12 code are
-// those of its base precision.
-bool prec_valid(tmh_prec p) { return p == TMH_F64 || p == TMH_F32 || p == TMH_F64_R12 || p == TMH_F32_R12; }
-tmh_prec base_prec(tmh_prec p) { return (p == TMH_F64 || p == TMH_F64_R12) ? TMH_F64 : TMH_F32; }
-int link_format(tmh_prec p) { return (p == TMH_F64_R12 || p == TMH_F32_R12) ? 1 : 0; }
+// A precision code is a storage word (FP64, FP32, or FP16 with FP32
+// arithmetic) and a link storage format (9 entries, or two rows for the _R12
+// codes); spinors of an _R12 code are those of its base precision.
+bool prec_valid(tmh_prec p) { return p >= TMH_F64 && p <= TMH_F16_R12; }
+tmh_prec base_prec(tmh_prec p) {
+    if (p == TMH_F64 || p == TMH_F64_R12) return TMH_F64;
+    if (p == TMH_F32 || p == TMH_F32_R12) return TMH_F32;
+    return TMH_F16;
+}
+int link_format(tmh_prec p) { return (p == TMH_F64_R12 || p == TMH_F32_R12 || p == TMH_F16_R12) ? 1 : 0; }
 int link_comps(tmh_prec p) { return link_format(p) ? 6 : 9; }
-size_t word_bytes(tmh_prec p) { return prec_valid(p) ? (base_prec(p) == TMH_F64 ? 16 : 8) : 0; }
+size_t word_bytes(tmh_prec p) {
+    if (!prec_valid(p)) return 0;
+    const tmh_prec b = base_prec(p);
+    return b == TMH_F64 ? 16 : (b == TMH_F32 ? 8 : 4);
+}
+// Slot of a base precision in per-precision scratch arrays.
+int prec_slot(tmh_prec p) {
+    const tmh_prec b = base_prec(p);
+    return b == TMH_F64 ? 0 : (b == TMH_F32 ? 1 : 2);
+}
+// The precision code of storage P with link format lf.
+template <typename P> int prec_code(int lf);
+template <> int prec_code<double>(int lf) { return lf ? TMH_F64_R12 : TMH_F64; }
+template <> int prec_code<float>(int lf) { return lf ? TMH_F32_R12 : TMH_F32; }
+template <> int prec_code<tmh::half_t>(int lf) { return lf ? TMH_F16_R12 : TMH_F16; }
+// Calls f with a value of the storage type of p's base precision.
+template <typename F> tmh_status dispatch(tmh_prec p, F&& f) {
+    const tmh_prec b = base_prec(p);
+    if (b == TMH_F64) return f(double{});
+    if (b == TMH_F32) return f(float{});
+    return f(tmh::half_t{});
+}
 
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
@@ -127,9 +152,9 @@ size_t gauge_bytes(const tmh_lattice* l, tmh_prec p) {
 }
 
 tmh_status even_scratch(tmh_lattice* l, tmh_prec p, void** out) {
-    p = base_prec(p);
-    TMH_TRY(ensure(&l->even[p], spinor_bytes(l, p)));
-    *out = l->even[p];
+    const int k = prec_slot(p);
+    TMH_TRY(ensure(&l->even[k], spinor_bytes(l, p)));
+    *out = l->even[k];
     return TMH_OK;
 }
 
@@ -154,8 +179,8 @@ HopArgs<R> hop_args(const tmh_lattice* l, int pout, void* out, const void* gauge
         a.nt = l->dims[0] / 8;
     }
     for (int m = 0; m < 4; ++m) {
-        a.ph_re[m] = (R)cos(M_PI * theta[m]);
-        a.ph_im[m] = (R)sin(M_PI * theta[m]);
+        a.ph_re[m] = (tmh::real_t<R>)cos(M_PI * theta[m]);
+        a.ph_im[m] = (tmh::real_t<R>)sin(M_PI * theta[m]);
     }
     return a;
 }
@@ -193,7 +218,7 @@ hipError_t hop_launch(tmh_lattice* l, const HopArgs<R>& a, int mode) {
             return hipErrorUnknown;
         }
     }
-    e.kind = 4 * ((sizeof(R) == 8 ? 0 : 1) + 2 * a.lf) + mode;
+    e.kind = 4 * prec_code<R>(a.lf) + mode;
     hipError_t err = hipEventRecord(e.start, l->stream);
     if (err == hipSuccess) err = tmh::launch_hop<R>(a, mode, l->stream);
     if (err == hipSuccess) err = hipEventRecord(e.stop, l->stream);
@@ -215,10 +240,10 @@ tmh_status qtm_launch(tmh_lattice* l, void* out, const void* gauge, const void* 
     HopArgs<R> a = hop_args<R>(l, 0, te, gauge, in, theta, lf);
     a.done = done;
     // A^-1 = (1 - i mt gamma_5)/D: upper spins (1 - i mt)/D, lower (1 + i mt)/D
-    a.c_re[0] = (R)(kappa / D);
-    a.c_im[0] = (R)(-kappa * mt / D);
-    a.c_re[1] = (R)(kappa / D);
-    a.c_im[1] = (R)(kappa * mt / D);
+    a.c_re[0] = (tmh::real_t<R>)(kappa / D);
+    a.c_im[0] = (tmh::real_t<R>)(-kappa * mt / D);
+    a.c_re[1] = (tmh::real_t<R>)(kappa / D);
+    a.c_im[1] = (tmh::real_t<R>)(kappa * mt / D);
     TMH_TRY_HIP(hop_launch<R>(l, a, 0));
     HopArgs<R> b = hop_args<R>(l, 1, out, gauge, te, theta, lf);
     b.done = done;
@@ -226,12 +251,12 @@ tmh_status qtm_launch(tmh_lattice* l, void* out, const void* gauge, const void* 
     b.partial = partial;
     // gamma_5 [A in - kappa H te]: upper (1 + i mt) in - kappa H te,
     // lower kappa H te - (1 - i mt) in
-    b.c_re[0] = (R)(-kappa);
-    b.c_re[1] = (R)kappa;
-    b.d_re[0] = (R)1;
-    b.d_im[0] = (R)mt;
-    b.d_re[1] = (R)-1;
-    b.d_im[1] = (R)mt;
+    b.c_re[0] = (tmh::real_t<R>)(-kappa);
+    b.c_re[1] = (tmh::real_t<R>)kappa;
+    b.d_re[0] = (tmh::real_t<R>)1;
+    b.d_im[0] = (tmh::real_t<R>)mt;
+    b.d_re[1] = (tmh::real_t<R>)-1;
+    b.d_im[1] = (tmh::real_t<R>)mt;
     TMH_TRY_HIP(hop_launch<R>(l, b, partial ? 2 : 1));
     return TMH_OK;
 }
@@ -274,10 +299,10 @@ tmh_status qtm_update(tmh_lattice* l, void* x, void* r, const void* p, const voi
     const double D = 1.0 + mt * mt;
     HopArgs<R> a = hop_args<R>(l, 0, te, gauge, v, theta, lf);
     a.done = done;
-    a.c_re[0] = (R)(kappa / D);
-    a.c_im[0] = (R)(-kappa * mt / D);
-    a.c_re[1] = (R)(kappa / D);
-    a.c_im[1] = (R)(kappa * mt / D);
+    a.c_re[0] = (tmh::real_t<R>)(kappa / D);
+    a.c_im[0] = (tmh::real_t<R>)(-kappa * mt / D);
+    a.c_re[1] = (tmh::real_t<R>)(kappa / D);
+    a.c_im[1] = (tmh::real_t<R>)(kappa * mt / D);
     TMH_TRY_HIP(hop_launch<R>(l, a, 0));
     HopArgs<R> b = hop_args<R>(l, 1, nullptr, gauge, te, theta, lf);
     b.done = done;
@@ -287,12 +312,12 @@ tmh_status qtm_update(tmh_lattice* l, void* x, void* r, const void* p, const voi
     b.rio = (W*)r;
     b.pin = (const W*)p;
     b.scal = l->scal;
-    b.c_re[0] = (R)(-kappa);
-    b.c_re[1] = (R)kappa;
-    b.d_re[0] = (R)1;
-    b.d_im[0] = (R)mt;
-    b.d_re[1] = (R)-1;
-    b.d_im[1] = (R)mt;
+    b.c_re[0] = (tmh::real_t<R>)(-kappa);
+    b.c_re[1] = (tmh::real_t<R>)kappa;
+    b.d_re[0] = (tmh::real_t<R>)1;
+    b.d_im[0] = (tmh::real_t<R>)mt;
+    b.d_re[1] = (tmh::real_t<R>)-1;
+    b.d_im[1] = (tmh::real_t<R>)mt;
     TMH_TRY_HIP(hop_launch<R>(l, b, 3));
     return TMH_OK;
 }
@@ -385,19 +410,24 @@ tmh_status alloc_cg64(tmh_lattice* l) {
     return even_scratch(l, TMH_F64, &te);
 }
 
-tmh_status alloc_cg32(tmh_lattice* l) {
-    for (int k = 0; k < 5; ++k) TMH_TRY(ensure((void**)&l->v32[k], spinor_bytes(l, TMH_F32)));
-    TMH_TRY(ensure((void**)&l->gauge32, gauge_bytes(l, TMH_F32)));
+// Precision of the inner solve of storage P (FP32 or FP16) and its slot.
+template <typename P> constexpr tmh_prec low_prec() { return sizeof(P) == 4 ? TMH_F32 : TMH_F16; }
+template <typename P> constexpr int low_slot() { return sizeof(P) == 4 ? 0 : 1; }
+
+template <typename P> tmh_status alloc_low(tmh_lattice* l) {
+    constexpr tmh_prec lp = low_prec<P>();
+    for (int k = 0; k < 5; ++k) TMH_TRY(ensure(&l->vlow[low_slot<P>()][k], spinor_bytes(l, lp)));
+    TMH_TRY(ensure(&l->glow[low_slot<P>()], gauge_bytes(l, lp)));
     void* te;
-    return even_scratch(l, TMH_F32, &te);
+    return even_scratch(l, lp, &te);
 }
 
 // Two-row copies of the links are used where every link's stored third row
 // matches the conjugate cross product of its first two to these bounds
-// (special unitary links): FP64 rounding of the entries for the FP64 solve,
-// FP32 rounding for the FP32 inner solve.  Otherwise all 9 entries are kept.
+// (special unitary links): below the rounding of the entries in the copy's
+// precision.  Otherwise all 9 entries are kept.
 constexpr double kR12Tol64 = 1e-14;
-constexpr double kR12Tol32 = 1e-7;
+template <typename P> constexpr double r12_tol() { return sizeof(P) == 4 ? 1e-7 : 1e-4; }
 
 // Largest deviation found by the last compress launch (waits).
 tmh_status link_deviation(tmh_lattice* l, double* dev) {
@@ -425,18 +455,19 @@ tmh_status links64(tmh_lattice* l, const void* gauge, bool r12, const void** use
     return TMH_OK;
 }
 
-// Narrows the FP64 links into l->gauge32: two rows with r12 when the links
-// pass the check (*lf = 1), else all 9 entries.
-tmh_status links32(tmh_lattice* l, const void* gauge, bool r12, int* lf) {
+// Narrows the FP64 links into the inner solve's copy (storage P): two rows
+// with r12 when the links pass the check (*lf = 1), else all 9 entries.
+template <typename P> tmh_status links_low(tmh_lattice* l, const void* gauge, bool r12, int* lf) {
+    using W = typename tmh::Word<P>::T;
+    W* dst = (W*)l->glow[low_slot<P>()];
     *lf = 0;
     if (r12) {
-        TMH_TRY_HIP(tmh::launch_compress_links<float>(l->gauge32, (const double2*)gauge, l->partial, l->g,
-                                                      l->stream));
+        TMH_TRY_HIP(tmh::launch_compress_links<P>(dst, (const double2*)gauge, l->partial, l->g, l->stream));
         double dev;
         TMH_TRY(link_deviation(l, &dev));
-        if (dev <= kR12Tol32) return *lf = 1, TMH_OK;
+        if (dev <= r12_tol<P>()) return *lf = 1, TMH_OK;
     }
-    TMH_TRY_HIP(tmh::launch_narrow(l->gauge32, (const double2*)gauge, 72, l->g, l->stream));
+    TMH_TRY_HIP(tmh::launch_narrow<P>(dst, (const double2*)gauge, 72, 1.0, l->g, l->stream));
     return TMH_OK;
 }
 
@@ -473,18 +504,29 @@ tmh_status cg_fp64(tmh_lattice* l, void* x, const void* b, const void* gauge, do
     return TMH_ERR_NOT_CONVERGED;
 }
 
-// Defect correction: FP64 true residual and solution update, FP32 inner CG.
-constexpr double kInnerTolMin = 1e-5;
+// Defect correction: FP64 true residual and solution update, inner CG in
+// FP32 or in FP16 storage.  The inner target is the remaining factor, but no
+// tighter than the inner precision can hold.
+#ifndef TMH_INNER_TOL_F16
+#define TMH_INNER_TOL_F16 3e-3
+#endif
+template <typename P> constexpr double inner_tol_min() { return sizeof(P) == 4 ? 1e-5 : TMH_INNER_TOL_F16; }
 constexpr int kMaxOuter = 64;
+// The inner system is scaled: FP32 takes the residual as it is, FP16 takes
+// it scaled to unit mean square per real component (so that the recursion's
+// vectors stay inside FP16's normal range); the correction is scaled back.
+template <typename P>
 tmh_status cg_mixed(tmh_lattice* l, void* x, const void* b, const void* gauge, double kappa, double mu,
                     const double theta[4], double tol, int max_iter, int* iters, double* res, bool r12) {
+    using W = typename tmh::Word<P>::T;
     TMH_TRY(alloc_cg64(l));
-    TMH_TRY(alloc_cg32(l));
-    void *r = l->v64[0], *v = l->v64[2], *q = l->v64[3], *te = l->even[TMH_F64];
-    float2 *r32 = l->v32[0], *p32 = l->v32[1], *v32 = l->v32[2], *q32 = l->v32[3], *d32 = l->v32[4];
-    void* te32 = l->even[TMH_F32];
+    TMH_TRY(alloc_low<P>(l));
+    void *r = l->v64[0], *v = l->v64[2], *q = l->v64[3], *te = l->even[0];
+    void** vl = l->vlow[low_slot<P>()];
+    W *rl = (W*)vl[0], *pl = (W*)vl[1], *vv = (W*)vl[2], *ql = (W*)vl[3], *dl = (W*)vl[4];
+    void* tel = l->even[prec_slot(low_prec<P>())];
     int lf = 0;
-    TMH_TRY(links32(l, gauge, r12, &lf));
+    TMH_TRY(links_low<P>(l, gauge, r12, &lf));
     double bb;
     TMH_TRY(reduce_dot<double>(l, &bb, b, b));
     *iters = 0;
@@ -500,22 +542,33 @@ tmh_status cg_mixed(tmh_lattice* l, void* x, const void* b, const void* gauge, d
     for (int outer = 0;; ++outer) {
         *res = sqrt(rr / bb);
         if (*res <= tol) return *iters = total, TMH_OK;
-        if (outer >= kMaxOuter || total >= max_iter) break;
-        // inner target: the remaining factor, but no tighter than FP32 can hold
+        if (outer >= kMaxOuter || total >= max_iter || !(rr > 0.0)) break;
         double inner = 0.5 * tol / *res;
-        if (inner < kInnerTolMin) inner = kInnerTolMin;
-        TMH_TRY_HIP(tmh::launch_narrow(r32, (const double2*)r, 12, l->g, l->stream));
-        TMH_TRY_HIP(tmh::launch_zero<float>(d32, l->g, l->stream));
+        if (inner < inner_tol_min<P>()) inner = inner_tol_min<P>();
+        const double scale = sizeof(P) == 4 ? 1.0 : sqrt(24.0 * l->g.Vh / rr);
+        TMH_TRY_HIP(tmh::launch_narrow<P>(rl, (const double2*)r, 12, scale, l->g, l->stream));
+        TMH_TRY_HIP(tmh::launch_zero<P>(dl, l->g, l->stream));
         int it = 0;
-        // |r32|^2 ~ rr; the stop test is relative to the narrowed residual
-        TMH_TRY(cg_recursion<float>(l, d32, r32, p32, v32, q32, te32, l->gauge32, kappa, mu, theta,
-                                    inner * inner * rr, max_iter - total, &it, lf));
+        // the stop test is relative to the scaled residual, |scale r|^2
+        TMH_TRY(cg_recursion<P>(l, dl, rl, pl, vv, ql, tel, l->glow[low_slot<P>()], kappa, mu, theta,
+                                inner * inner * scale * scale * rr, max_iter - total, &it, lf));
         total += it;
-        TMH_TRY_HIP(tmh::launch_add_widen((double2*)x, d32, l->g, l->stream));
+        TMH_TRY_HIP(tmh::launch_add_widen<P>((double2*)x, dl, 1.0 / scale, l->g, l->stream));
         TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
     }
     *iters = total;
     return TMH_ERR_NOT_CONVERGED;
+}
+
+// Runs the solver that `inner` names.
+tmh_status cg_dispatch(tmh_lattice* l, void* x, const void* b, const void* gauge, double kappa, double mu,
+                       const double theta[4], double tol, int max_iter, tmh_prec inner, int* iters, double* res) {
+    const bool r12 = link_format(inner) == 1;
+    switch (base_prec(inner)) {
+        case TMH_F64: return cg_fp64(l, x, b, gauge, kappa, mu, theta, tol, max_iter, iters, res, r12);
+        case TMH_F32: return cg_mixed<float>(l, x, b, gauge, kappa, mu, theta, tol, max_iter, iters, res, r12);
+        default: return cg_mixed<tmh::half_t>(l, x, b, gauge, kappa, mu, theta, tol, max_iter, iters, res, r12);
+    }
 }
 
 }  // namespace
@@ -582,8 +635,9 @@ void tmh_lattice_destroy(tmh_lattice* l) {
     for (void* p : l->odd_rhs) (void)hipFree(p);
     for (void* p : l->mrhs) (void)hipFree(p);
     for (void* p : l->v64) (void)hipFree(p);
-    for (void* p : l->v32) (void)hipFree(p);
-    (void)hipFree(l->gauge32);
+    for (auto& vs : l->vlow)
+        for (void* p : vs) (void)hipFree(p);
+    for (void* p : l->glow) (void)hipFree(p);
     (void)hipFree(l->gauge64r12);
     (void)prof_flush(l);
     for (auto& e : l->prof_free) {
@@ -620,15 +674,14 @@ tmh_status tmh_gauge_import(tmh_lattice* l, void* dst, const double* src, tmh_pr
     if (!dst || !src) return TMH_ERR_ARG;
     if (overlap(dst, gauge_bytes(l, prec), src, (size_t)2 * l->g.Vh * 4 * 9 * 16)) return TMH_ERR_ALIAS;
     DeviceGuard guard(l->device);
-    if (prec == TMH_F64)
-        TMH_TRY_HIP(tmh::launch_gauge_import<double>((double2*)dst, src, l->g, l->stream));
-    else if (prec == TMH_F32)
-        TMH_TRY_HIP(tmh::launch_gauge_import<float>((float2*)dst, src, l->g, l->stream));
-    else if (prec == TMH_F64_R12)
-        TMH_TRY_HIP(tmh::launch_gauge_import_r12<double>((double2*)dst, src, l->g, l->stream));
-    else
-        TMH_TRY_HIP(tmh::launch_gauge_import_r12<float>((float2*)dst, src, l->g, l->stream));
-    return TMH_OK;
+    const bool r12 = link_format(prec) == 1;
+    return dispatch(prec, [&](auto tag) {
+        using P = decltype(tag);
+        using W = typename tmh::Word<P>::T;
+        TMH_TRY_HIP(r12 ? tmh::launch_gauge_import_r12<P>((W*)dst, src, l->g, l->stream)
+                        : tmh::launch_gauge_import<P>((W*)dst, src, l->g, l->stream));
+        return TMH_OK;
+    });
 }
 
 tmh_status tmh_spinor_import(tmh_lattice* l, void* dst, const double* src, tmh_prec prec) {
@@ -637,11 +690,11 @@ tmh_status tmh_spinor_import(tmh_lattice* l, void* dst, const double* src, tmh_p
     if (!dst || !src) return TMH_ERR_ARG;
     if (overlap(dst, spinor_bytes(l, prec), src, (size_t)l->g.Vh * 12 * 16)) return TMH_ERR_ALIAS;
     DeviceGuard guard(l->device);
-    if (base_prec(prec) == TMH_F64)
-        TMH_TRY_HIP(tmh::launch_spinor_import<double>((double2*)dst, src, l->g, l->stream));
-    else
-        TMH_TRY_HIP(tmh::launch_spinor_import<float>((float2*)dst, src, l->g, l->stream));
-    return TMH_OK;
+    return dispatch(prec, [&](auto tag) {
+        using P = decltype(tag);
+        TMH_TRY_HIP(tmh::launch_spinor_import<P>((typename tmh::Word<P>::T*)dst, src, l->g, l->stream));
+        return TMH_OK;
+    });
 }
 
 tmh_status tmh_spinor_export(tmh_lattice* l, double* dst, const void* src, tmh_prec prec) {
@@ -650,11 +703,11 @@ tmh_status tmh_spinor_export(tmh_lattice* l, double* dst, const void* src, tmh_p
     if (!dst || !src) return TMH_ERR_ARG;
     if (overlap(dst, (size_t)l->g.Vh * 12 * 16, src, spinor_bytes(l, prec))) return TMH_ERR_ALIAS;
     DeviceGuard guard(l->device);
-    if (base_prec(prec) == TMH_F64)
-        TMH_TRY_HIP(tmh::launch_spinor_export<double>(dst, (const double2*)src, l->g, l->stream));
-    else
-        TMH_TRY_HIP(tmh::launch_spinor_export<float>(dst, (const float2*)src, l->g, l->stream));
-    return TMH_OK;
+    return dispatch(prec, [&](auto tag) {
+        using P = decltype(tag);
+        TMH_TRY_HIP(tmh::launch_spinor_export<P>(dst, (const typename tmh::Word<P>::T*)src, l->g, l->stream));
+        return TMH_OK;
+    });
 }
 
 tmh_status tmh_hop_apply(tmh_lattice* l, tmh_dir dir, void* out, const void* gauge, const void* in, double kappa,
@@ -669,16 +722,13 @@ tmh_status tmh_hop_apply(tmh_lattice* l, tmh_dir dir, void* out, const void* gau
     DeviceGuard guard(l->device);
     const int pout = dir == TMH_EO ? 0 : 1;
     const int lf = link_format(prec);
-    if (base_prec(prec) == TMH_F64) {
-        HopArgs<double> a = hop_args<double>(l, pout, out, gauge, in, theta, lf);
-        a.c_re[0] = a.c_re[1] = kappa;
-        TMH_TRY_HIP(hop_launch<double>(l, a, 0));
-    } else {
-        HopArgs<float> a = hop_args<float>(l, pout, out, gauge, in, theta, lf);
-        a.c_re[0] = a.c_re[1] = (float)kappa;
-        TMH_TRY_HIP(hop_launch<float>(l, a, 0));
-    }
-    return TMH_OK;
+    return dispatch(prec, [&](auto tag) {
+        using P = decltype(tag);
+        HopArgs<P> a = hop_args<P>(l, pout, out, gauge, in, theta, lf);
+        a.c_re[0] = a.c_re[1] = (tmh::real_t<P>)kappa;
+        TMH_TRY_HIP(hop_launch<P>(l, a, 0));
+        return TMH_OK;
+    });
 }
 
 tmh_status tmh_qtm_apply(tmh_lattice* l, void* out, const void* gauge, const void* in, double kappa, double mu,
@@ -694,9 +744,10 @@ tmh_status tmh_qtm_apply(tmh_lattice* l, void* out, const void* gauge, const voi
     void* te;
     TMH_TRY(even_scratch(l, prec, &te));
     const int lf = link_format(prec);
-    if (base_prec(prec) == TMH_F64)
-        return qtm_launch<double>(l, out, gauge, in, te, kappa, mu, theta, sign, nullptr, nullptr, lf);
-    return qtm_launch<float>(l, out, gauge, in, te, kappa, mu, theta, sign, nullptr, nullptr, lf);
+    return dispatch(prec, [&](auto tag) {
+        using P = decltype(tag);
+        return qtm_launch<P>(l, out, gauge, in, te, kappa, mu, theta, sign, nullptr, nullptr, lf);
+    });
 }
 
 tmh_status tmh_cg_solve(tmh_lattice* l, void* x, const void* b, const void* gauge, double kappa, double mu,
@@ -710,10 +761,7 @@ tmh_status tmh_cg_solve(tmh_lattice* l, void* x, const void* b, const void* gaug
     const size_t sb = spinor_bytes(l, TMH_F64);
     if (overlap(x, sb, b, sb) || overlap(x, sb, gauge, gauge_bytes(l, TMH_F64))) return TMH_ERR_ALIAS;
     DeviceGuard guard(l->device);
-    const bool r12 = link_format(inner) == 1;
-    tmh_status st = base_prec(inner) == TMH_F64
-                        ? cg_fp64(l, x, b, gauge, kappa, mu, theta, rel_tol, max_iter, iters, true_rel_res, r12)
-                        : cg_mixed(l, x, b, gauge, kappa, mu, theta, rel_tol, max_iter, iters, true_rel_res, r12);
+    tmh_status st = cg_dispatch(l, x, b, gauge, kappa, mu, theta, rel_tol, max_iter, inner, iters, true_rel_res);
     if (hipStreamSynchronize(l->stream) != hipSuccess) return TMH_ERR_HIP;
     return st;
 }
@@ -808,12 +856,8 @@ tmh_status tmh_solve_full(tmh_lattice* l, void* x_even, void* x_odd, const void*
     TMH_TRY(even_scratch(l, TMH_F64, &te));
     TMH_TRY(qtm_launch<double>(l, l->odd_rhs[1], gauge, l->odd_rhs[0], te, kappa, mu, theta, -1, nullptr,
                                nullptr));
-    const bool r12 = link_format(inner) == 1;
-    tmh_status st = base_prec(inner) == TMH_F64
-                        ? cg_fp64(l, x_odd, l->odd_rhs[1], gauge, kappa, mu, theta, rel_tol, max_iter, iters,
-                                  true_rel_res, r12)
-                        : cg_mixed(l, x_odd, l->odd_rhs[1], gauge, kappa, mu, theta, rel_tol, max_iter, iters,
-                                   true_rel_res, r12);
+    tmh_status st = cg_dispatch(l, x_odd, l->odd_rhs[1], gauge, kappa, mu, theta, rel_tol, max_iter, inner, iters,
+                                true_rel_res);
     if (st != TMH_OK && st != TMH_ERR_NOT_CONVERGED) return st;
     // x_e = A^-1 (b_e + H_eo x_o)
     HopArgs<double> b = hop_args<double>(l, 0, x_even, gauge, x_odd, theta);
@@ -1292,7 +1336,7 @@ tmh_status tmh_autotune_hop(tmh_lattice* l, const void* gauge, tmh_prec prec, co
     const size_t sp = arch.find(':');
     if (sp != std::string::npos) arch = arch.substr(0, sp);
     char key[256];
-    static const char* const kPrecName[4] = {"f64", "f32", "f64r12", "f32r12"};
+    static const char* const kPrecName[6] = {"f64", "f32", "f64r12", "f32r12", "f16", "f16r12"};
     snprintf(key, sizeof key, "%s %dx%dx%dx%d %s hop", arch.c_str(), l->dims[0], l->dims[1], l->dims[2], l->dims[3],
              kPrecName[prec]);
     if (cache_path) {
@@ -1378,15 +1422,14 @@ tmh_status tmh_gauge_export(tmh_lattice* l, double* dst, const void* src, tmh_pr
     if (!dst || !src) return TMH_ERR_ARG;
     if (overlap(dst, (size_t)2 * l->g.Vh * 4 * 9 * 16, src, gauge_bytes(l, prec))) return TMH_ERR_ALIAS;
     DeviceGuard guard(l->device);
-    if (prec == TMH_F64)
-        TMH_TRY_HIP(tmh::launch_gauge_export<double>(dst, (const double2*)src, l->g, l->stream));
-    else if (prec == TMH_F32)
-        TMH_TRY_HIP(tmh::launch_gauge_export<float>(dst, (const float2*)src, l->g, l->stream));
-    else if (prec == TMH_F64_R12)
-        TMH_TRY_HIP(tmh::launch_gauge_export_r12<double>(dst, (const double2*)src, l->g, l->stream));
-    else
-        TMH_TRY_HIP(tmh::launch_gauge_export_r12<float>(dst, (const float2*)src, l->g, l->stream));
-    return TMH_OK;
+    const bool r12 = link_format(prec) == 1;
+    return dispatch(prec, [&](auto tag) {
+        using P = decltype(tag);
+        using W = typename tmh::Word<P>::T;
+        TMH_TRY_HIP(r12 ? tmh::launch_gauge_export_r12<P>(dst, (const W*)src, l->g, l->stream)
+                        : tmh::launch_gauge_export<P>(dst, (const W*)src, l->g, l->stream));
+        return TMH_OK;
+    });
 }
 
 tmh_status tmh_scalar_prod_r(tmh_lattice* l, double* result, const void* a, const void* b, tmh_prec prec) {
@@ -1394,7 +1437,7 @@ tmh_status tmh_scalar_prod_r(tmh_lattice* l, double* result, const void* a, cons
     TMH_TRY(check_prec(prec));
     if (!result || !a || !b) return TMH_ERR_ARG;
     DeviceGuard guard(l->device);
-    return base_prec(prec) == TMH_F64 ? reduce_dot<double>(l, result, a, b) : reduce_dot<float>(l, result, a, b);
+    return dispatch(prec, [&](auto tag) { return reduce_dot<decltype(tag)>(l, result, a, b); });
 }
 
 tmh_status tmh_norm2(tmh_lattice* l, double* result, const void* a, tmh_prec prec) {

@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(kBlock) cg_xr_kernel(typename Word<R>::T* __re
                                                        const double* __restrict__ scal, double* __restrict__ partial,
                                                        Geo g, const int* flags) {
     if (is_done(flags)) return;
-    const R alpha = (R)scal[kAlpha];
+    const real_t<R> alpha = (real_t<R>)scal[kAlpha];
     double s = 0.0;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < g.Vh; i += gridDim.x * kBlock) {
 #pragma unroll
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(kBlock) cg_p_kernel(typename Word<R>::T* __res
                                                       const typename Word<R>::T* __restrict__ r,
                                                       const double* __restrict__ scal, Geo g, const int* flags) {
     if (is_done(flags)) return;
-    const R beta = (R)scal[kBeta];
+    const real_t<R> beta = (real_t<R>)scal[kBeta];
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < g.Vh; i += gridDim.x * kBlock) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
@@ -160,16 +160,18 @@ __global__ void __launch_bounds__(kBlock) sub_norm_kernel(typename Word<R>::T* _
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(kBlock) add_widen_kernel(double2* __restrict__ x, const float2* __restrict__ y,
+template <typename P>
+__global__ void __launch_bounds__(kBlock) add_widen_kernel(double2* __restrict__ x,
+                                                           const typename Word<P>::T* __restrict__ y, double scale,
                                                            Geo g) {
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < g.Vh; i += gridDim.x * kBlock) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
             const int64_t k = (int64_t)c * g.S + i;
             double2 v = x[k];
-            const float2 w = y[k];
-            v.x += (double)w.x;
-            v.y += (double)w.y;
+            const auto w = y[k];
+            v.x += scale * (double)w.x;
+            v.y += scale * (double)w.y;
             x[k] = v;
         }
     }
@@ -305,8 +307,9 @@ hipError_t launch_chiral_scale(double2* out, const double2* in, double cu_re, do
     return hipGetLastError();
 }
 
-hipError_t launch_add_widen(double2* x, const float2* y, const Geo& g, hipStream_t s) {
-    hipLaunchKernelGGL(add_widen_kernel, dim3(blas_blocks(g)), dim3(kBlock), 0, s, x, y, g);
+template <typename P>
+hipError_t launch_add_widen(double2* x, const typename Word<P>::T* y, double scale, const Geo& g, hipStream_t s) {
+    hipLaunchKernelGGL((add_widen_kernel<P>), dim3(blas_blocks(g)), dim3(kBlock), 0, s, x, y, scale, g);
     return hipGetLastError();
 }
 
@@ -337,6 +340,9 @@ hipError_t launch_zero(typename Word<R>::T* dst, const Geo& g, hipStream_t s) {
 
 TMH_INST(double)
 TMH_INST(float)
+TMH_INST(half_t)
 #undef TMH_INST
+template hipError_t launch_add_widen<float>(double2*, const float2*, double, const Geo&, hipStream_t);
+template hipError_t launch_add_widen<half_t>(double2*, const h2*, double, const Geo&, hipStream_t);
 
 }  // namespace tmh

@@ -10,10 +10,21 @@ namespace tmh {
 constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
 constexpr int kXcds = 8;     // MI355X: 8 XCDs, workgroups dealt round-robin
 
+// Storage precision P of a field: double and float store and compute in
+// that type; half_t stores FP16 and computes in FP32.
+struct half_t {};
+template <typename P> struct Math { using R = P; };
+template <> struct Math<half_t> { using R = float; };
+template <typename P> using real_t = typename Math<P>::R;
+
 // Storage word of one complex number.
+struct alignas(4) h2 {
+    _Float16 x, y;
+};
 template <typename R> struct Word;
 template <> struct Word<double> { using T = double2; };
 template <> struct Word<float> { using T = float2; };
+template <> struct Word<half_t> { using T = h2; };
 
 template <typename R> struct cx {
     R re, im;
@@ -138,20 +149,38 @@ template <> struct BufIO<float> {
     }
 };
 
-// Complex element `i` of the component array starting at `base` (S words).
-template <typename R, int AUX = 0>
-__device__ __forceinline__ cx<R> bload(const typename Word<R>::T* base, int S, int i) {
-    const unsigned wb = sizeof(typename Word<R>::T);
-    const auto w = BufIO<R>::template load<AUX>(buf_rsrc(base, (unsigned)S * wb), (unsigned)i * wb);
-    return {w.x, w.y};
+template <> struct BufIO<half_t> {
+    template <int AUX>
+    __device__ static __forceinline__ h2 load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX);
+        h2 w;
+        __builtin_memcpy(&w, &v, sizeof w);
+        return w;
+    }
+    template <int AUX>
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, unsigned off, h2 w) {
+        unsigned int v;
+        __builtin_memcpy(&v, &w, sizeof w);
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, AUX);
+    }
+};
+
+// Element `i` of the component array starting at `base` (S words), widened
+// to the arithmetic type of P.
+template <typename P, int AUX = 0>
+__device__ __forceinline__ cx<real_t<P>> bload(const typename Word<P>::T* base, int S, int i) {
+    const unsigned wb = sizeof(typename Word<P>::T);
+    const auto w = BufIO<P>::template load<AUX>(buf_rsrc(base, (unsigned)S * wb), (unsigned)i * wb);
+    return {(real_t<P>)w.x, (real_t<P>)w.y};
 }
-template <typename R, int AUX = 0>
-__device__ __forceinline__ void bstore(typename Word<R>::T* base, int S, int i, cx<R> v) {
-    const unsigned wb = sizeof(typename Word<R>::T);
-    typename Word<R>::T w;
+// Stores v rounded to the storage type of P (round to nearest even).
+template <typename P, int AUX = 0>
+__device__ __forceinline__ void bstore(typename Word<P>::T* base, int S, int i, cx<real_t<P>> v) {
+    const unsigned wb = sizeof(typename Word<P>::T);
+    typename Word<P>::T w;
     w.x = v.re;
     w.y = v.im;
-    BufIO<R>::template store<AUX>(buf_rsrc(base, (unsigned)S * wb), (unsigned)i * wb, w);
+    BufIO<P>::template store<AUX>(buf_rsrc(base, (unsigned)S * wb), (unsigned)i * wb, w);
 }
 
 // Lattice extents and strides as seen by the kernels.

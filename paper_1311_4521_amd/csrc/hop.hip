@@ -52,8 +52,9 @@ __device__ __forceinline__ int unit_site(int b, int w, int nb, int xgroup, int n
 #endif
 }
 
-template <typename R, int MODE, int LF>
-__global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> a) {
+template <typename P, int MODE, int LF>
+__global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<P> a) {
+    using R = real_t<P>;
     if (a.done && *a.done) return;
     const int i = unit_site(blockIdx.x, threadIdx.x >> 6, gridDim.x, a.xgroup, a.nyb, a.nt, a.g.L[1]) +
                   (threadIdx.x & 63);
@@ -67,7 +68,7 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> 
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc[s][k] = mk<R>(0, 0);
         const SiteNb n = site_neighbours(a.g, c, lex);
-        hop_site<R, TMH_HOP_PIPE != 0, kLinkAux, LF>(acc, a, n, i);
+        hop_site<P, TMH_HOP_PIPE != 0, kLinkAux, LF>(acc, a, n, i);
         const int S = a.g.S;
         const R alpha = MODE == 3 ? (R)a.scal[kAlpha] : (R)0;
 #pragma unroll
@@ -78,19 +79,19 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> 
                 const int64_t comp = (int64_t)(3 * s + k) * S;
                 cx<R> o = cc * acc[s][k];
                 if constexpr (MODE >= 1)
-                    o += mk<R>(a.d_re[s >> 1], a.d_im[s >> 1]) * bload<R, out_aux<R>()>(a.aux + comp, S, i);
+                    o += mk<R>(a.d_re[s >> 1], a.d_im[s >> 1]) * bload<P, out_aux<P>()>(a.aux + comp, S, i);
                 if constexpr (MODE == 2) nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
                 if constexpr (MODE == 3) {
-                    cx<R> r = bload<R>(a.rio + comp, S, i);
-                    cx<R> x = bload<R>(a.xio + comp, S, i);
-                    const cx<R> p = bload<R>(a.pin + comp, S, i);
+                    cx<R> r = bload<P>(a.rio + comp, S, i);
+                    cx<R> x = bload<P>(a.xio + comp, S, i);
+                    const cx<R> p = bload<P>(a.pin + comp, S, i);
                     r -= alpha * o;
                     x += alpha * p;
-                    bstore<R>(a.rio + comp, S, i, r);
-                    bstore<R>(a.xio + comp, S, i, x);
+                    bstore<P>(a.rio + comp, S, i, r);
+                    bstore<P>(a.xio + comp, S, i, x);
                     nrm += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
                 } else {
-                    bstore<R, out_aux<R>()>(a.out + comp, S, i, o);
+                    bstore<P, out_aux<P>()>(a.out + comp, S, i, o);
                 }
             }
         }
@@ -103,25 +104,26 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<R> 
 
 int hop_blocks(const Geo& g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
 
-template <typename R, int LF>
-static hipError_t launch_hop_lf(const HopArgs<R>& a, int mode, int nb, hipStream_t stream) {
+template <typename P, int LF>
+static hipError_t launch_hop_lf(const HopArgs<P>& a, int mode, int nb, hipStream_t stream) {
     switch (mode) {
-        case 0: hipLaunchKernelGGL((hop_kernel<R, 0, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
-        case 1: hipLaunchKernelGGL((hop_kernel<R, 1, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
-        case 2: hipLaunchKernelGGL((hop_kernel<R, 2, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
-        default: hipLaunchKernelGGL((hop_kernel<R, 3, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        case 0: hipLaunchKernelGGL((hop_kernel<P, 0, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        case 1: hipLaunchKernelGGL((hop_kernel<P, 1, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        case 2: hipLaunchKernelGGL((hop_kernel<P, 2, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        default: hipLaunchKernelGGL((hop_kernel<P, 3, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
     }
     return hipGetLastError();
 }
 
-template <typename R>
-hipError_t launch_hop(const HopArgs<R>& a, int mode, hipStream_t stream) {
+template <typename P>
+hipError_t launch_hop(const HopArgs<P>& a, int mode, hipStream_t stream) {
     const int nb = hop_blocks(a.g);
     if (nb == 0) return hipSuccess;
-    return a.lf ? launch_hop_lf<R, 1>(a, mode, nb, stream) : launch_hop_lf<R, 0>(a, mode, nb, stream);
+    return a.lf ? launch_hop_lf<P, 1>(a, mode, nb, stream) : launch_hop_lf<P, 0>(a, mode, nb, stream);
 }
 
 template hipError_t launch_hop<double>(const HopArgs<double>&, int, hipStream_t);
 template hipError_t launch_hop<float>(const HopArgs<float>&, int, hipStream_t);
+template hipError_t launch_hop<half_t>(const HopArgs<half_t>&, int, hipStream_t);
 
 }  // namespace tmh

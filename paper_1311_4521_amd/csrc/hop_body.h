@@ -54,7 +54,7 @@ namespace tmh {
 // Cache policy of the link loads: each link is read once per application,
 // so a non-temporal hint keeps it from displacing neighbour spinors.
 constexpr int kLinkAux = TMH_HOP_NT_LINKS ? 2 : 0;
-template <typename R> constexpr int out_aux() { return (TMH_HOP_NT_STORE && sizeof(R) == 8) ? 2 : 0; }
+template <typename P> constexpr int out_aux() { return (TMH_HOP_NT_STORE && sizeof(P) == 8) ? 2 : 0; }
 constexpr int kHopBlock = TMH_HOP_BLOCK;
 static_assert(kHopBlock == kHopThreads, "the host sizes hop launches with kHopThreads");
 
@@ -79,16 +79,16 @@ __device__ __forceinline__ void third_row(cx<R> (&u)[3][3]) {
     u[2][2] = mk<R>(c2.re, -c2.im);
 }
 
-template <typename R, int LAUX, int LF>
-__device__ __forceinline__ void load_term(TermData<R>& d, const typename Word<R>::T* __restrict__ in,
-                                          const typename Word<R>::T* __restrict__ link, int S, int jn, int jl) {
+template <typename P, int LAUX, int LF>
+__device__ __forceinline__ void load_term(TermData<real_t<P>>& d, const typename Word<P>::T* __restrict__ in,
+                                          const typename Word<P>::T* __restrict__ link, int S, int jn, int jl) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) d.psi[s][a] = bload<R>(in + (int64_t)(3 * s + a) * S, S, jn);
+        for (int a = 0; a < 3; ++a) d.psi[s][a] = bload<P>(in + (int64_t)(3 * s + a) * S, S, jn);
 #pragma unroll
-    for (int k = 0; k < link_comps<LF>(); ++k) d.u[k / 3][k % 3] = bload<R, LAUX>(link + (int64_t)k * S, S, jl);
-    if constexpr (LF == 1) third_row<R>(d.u);
+    for (int k = 0; k < link_comps<LF>(); ++k) d.u[k / 3][k % 3] = bload<P, LAUX>(link + (int64_t)k * S, S, jl);
+    if constexpr (LF == 1) third_row<real_t<P>>(d.u);
 }
 
 // One of the 8 terms: DIR = +1 adds (1 - gamma_mu) U_mu(x) psi(x+mu),
@@ -169,19 +169,20 @@ __device__ __forceinline__ SiteNb site_neighbours(const Geo& g, const int c[4], 
 // Term t = 2*mu + b: forward (b = 0) uses U_mu(x) from the output parity at
 // the site's own index i; backward (b = 1) uses U_mu(x - mu) from the input
 // parity at the neighbour's index.
-template <typename R, int T, int LAUX, int LF>
-__device__ __forceinline__ void load_t(TermData<R>& d, const HopArgs<R>& a, const SiteNb& n, int i) {
+template <typename P, int T, int LAUX, int LF>
+__device__ __forceinline__ void load_t(TermData<real_t<P>>& d, const HopArgs<P>& a, const SiteNb& n, int i) {
     constexpr int MU = T / 2;
     constexpr int NC = link_comps<LF>();
     if constexpr (T % 2 == 0)
-        load_term<R, LAUX, LF>(d, a.in, a.gout + (int64_t)MU * NC * a.g.S, a.g.S, n.jn[T], i);
+        load_term<P, LAUX, LF>(d, a.in, a.gout + (int64_t)MU * NC * a.g.S, a.g.S, n.jn[T], i);
     else
-        load_term<R, LAUX, LF>(d, a.in, a.gin + (int64_t)MU * NC * a.g.S, a.g.S, n.jn[T], n.jn[T]);
+        load_term<P, LAUX, LF>(d, a.in, a.gin + (int64_t)MU * NC * a.g.S, a.g.S, n.jn[T], n.jn[T]);
 }
 
-template <typename R, int T>
-__device__ __forceinline__ void add_t(cx<R> (&acc)[4][3], const TermData<R>& d, const HopArgs<R>& a,
-                                      const SiteNb& n) {
+template <typename P, int T>
+__device__ __forceinline__ void add_t(cx<real_t<P>> (&acc)[4][3], const TermData<real_t<P>>& d,
+                                      const HopArgs<P>& a, const SiteNb& n) {
+    using R = real_t<P>;
     constexpr int MU = T / 2;
     const bool wrap = (n.wrap >> T) & 1u;
     if constexpr (T % 2 == 0)
@@ -199,46 +200,48 @@ __device__ __forceinline__ void add_t(cx<R> (&acc)[4][3], const TermData<R>& d, 
 // Sum of the 8 terms.  PIPE loads term t+1 before computing term t (two
 // register sets); otherwise each term is loaded and consumed in turn.  LAUX
 // is the cache policy of the link loads.
-template <typename R, bool PIPE, int LAUX = kLinkAux, int LF = 0>
-__device__ __forceinline__ void hop_site(cx<R> (&acc)[4][3], const HopArgs<R>& a, const SiteNb& n, int i) {
+template <typename P, bool PIPE, int LAUX = kLinkAux, int LF = 0>
+__device__ __forceinline__ void hop_site(cx<real_t<P>> (&acc)[4][3], const HopArgs<P>& a, const SiteNb& n,
+                                         int i) {
+    using R = real_t<P>;
     if constexpr (PIPE) {
     TermData<R> d0, d1;
-    load_t<R, 0, LAUX, LF>(d0, a, n, i);
+    load_t<P, 0, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
-    load_t<R, 1, LAUX, LF>(d1, a, n, i);
+    load_t<P, 1, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<R, 0>(acc, d0, a, n);
+    add_t<P, 0>(acc, d0, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 2, LAUX, LF>(d0, a, n, i);
+    load_t<P, 2, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<R, 1>(acc, d1, a, n);
+    add_t<P, 1>(acc, d1, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 3, LAUX, LF>(d1, a, n, i);
+    load_t<P, 3, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<R, 2>(acc, d0, a, n);
+    add_t<P, 2>(acc, d0, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 4, LAUX, LF>(d0, a, n, i);
+    load_t<P, 4, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<R, 3>(acc, d1, a, n);
+    add_t<P, 3>(acc, d1, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 5, LAUX, LF>(d1, a, n, i);
+    load_t<P, 5, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<R, 4>(acc, d0, a, n);
+    add_t<P, 4>(acc, d0, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 6, LAUX, LF>(d0, a, n, i);
+    load_t<P, 6, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<R, 5>(acc, d1, a, n);
+    add_t<P, 5>(acc, d1, a, n);
     TMH_SCHED_FENCE();
-    load_t<R, 7, LAUX, LF>(d1, a, n, i);
+    load_t<P, 7, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<R, 6>(acc, d0, a, n);
+    add_t<P, 6>(acc, d0, a, n);
     TMH_SCHED_FENCE();
-    add_t<R, 7>(acc, d1, a, n);
+    add_t<P, 7>(acc, d1, a, n);
     } else {
     TermData<R> d;
 #define TMH_TERM(T)              \
-    load_t<R, T, LAUX, LF>(d, a, n, i);    \
-    add_t<R, T>(acc, d, a, n);   \
+    load_t<P, T, LAUX, LF>(d, a, n, i);    \
+    add_t<P, T>(acc, d, a, n);   \
     TMH_SCHED_FENCE();
     TMH_TERM(0) TMH_TERM(1) TMH_TERM(2) TMH_TERM(3) TMH_TERM(4) TMH_TERM(5) TMH_TERM(6) TMH_TERM(7)
 #undef TMH_TERM

@@ -8,16 +8,19 @@
 
 namespace tmh {
 
-template <typename R> struct HopArgs {
-    typename Word<R>::T* out;
-    const typename Word<R>::T* in;
-    const typename Word<R>::T* gout;  // links U_mu(x) of the output parity
-    const typename Word<R>::T* gin;   // links U_mu(y) of the input parity
-    const typename Word<R>::T* aux;   // MODE >= 1: field added at the output site
+// Arguments of one hopping-matrix launch on fields of storage precision P
+// (double, float or half_t), arithmetic in real_t<P>.
+template <typename P> struct HopArgs {
+    using R = real_t<P>;
+    typename Word<P>::T* out;
+    const typename Word<P>::T* in;
+    const typename Word<P>::T* gout;  // links U_mu(x) of the output parity
+    const typename Word<P>::T* gin;   // links U_mu(y) of the input parity
+    const typename Word<P>::T* aux;   // MODE >= 1: field added at the output site
     double* partial;                  // MODE 2: per-workgroup |out|^2; MODE 3: |r|^2
-    typename Word<R>::T* xio;         // MODE 3: x += alpha p
-    typename Word<R>::T* rio;         // MODE 3: r -= alpha out (out itself is not stored)
-    const typename Word<R>::T* pin;   // MODE 3: p
+    typename Word<P>::T* xio;         // MODE 3: x += alpha p
+    typename Word<P>::T* rio;         // MODE 3: r -= alpha out (out itself is not stored)
+    const typename Word<P>::T* pin;   // MODE 3: p
     const double* scal;               // MODE 3: alpha = scal[kAlpha]
     const int* done;                  // optional device flag: skip when set
     Geo g;
@@ -71,9 +74,11 @@ hipError_t launch_compress_links(typename Word<R>::T* dst, const double2* src, d
 int link_check_blocks(const Geo& g);
 // out[0] = max(partial[0..n))
 hipError_t launch_reduce_max(double* out, const double* partial, int n, hipStream_t s);
-// Internal FP64 -> FP32 (spinor: ncomp = 12, gauge: ncomp = 72), and FP32 -> FP64.
-hipError_t launch_narrow(float2* dst, const double2* src, int ncomp, const Geo& g, hipStream_t s);
-hipError_t launch_widen(double2* dst, const float2* src, int ncomp, const Geo& g, hipStream_t s);
+// Internal FP64 -> storage of P (spinor: ncomp = 12, gauge: ncomp = 72),
+// every value multiplied by `scale` first.
+template <typename P>
+hipError_t launch_narrow(typename Word<P>::T* dst, const double2* src, int ncomp, double scale, const Geo& g,
+                         hipStream_t s);
 
 // BLAS-1 and reductions (blas.hip).  All reductions write per-workgroup
 // partials; reduce_partials sums them in a fixed order into out[0].
@@ -104,8 +109,9 @@ hipError_t launch_sub_norm(typename Word<R>::T* out, const typename Word<R>::T* 
 // out_s = c_up in_s (spins 0,1) or c_dn in_s (spins 2,3), FP64.
 hipError_t launch_chiral_scale(double2* out, const double2* in, double cu_re, double cu_im, double cd_re,
                                double cd_im, const Geo& g, hipStream_t s);
-// x += y (FP64 x, FP32 y): defect-correction update.
-hipError_t launch_add_widen(double2* x, const float2* y, const Geo& g, hipStream_t s);
+// x += scale * y (FP64 x, y of storage P): defect-correction update.
+template <typename P>
+hipError_t launch_add_widen(double2* x, const typename Word<P>::T* y, double scale, const Geo& g, hipStream_t s);
 template <typename R>
 hipError_t launch_copy(typename Word<R>::T* dst, const typename Word<R>::T* src, const Geo& g, hipStream_t s);
 template <typename R>

@@ -11,10 +11,11 @@ namespace tmh {
 
 namespace {
 
-template <typename R> __device__ __forceinline__ typename Word<R>::T cvt(double re, double im) {
-    typename Word<R>::T w;
-    w.x = (R)re;
-    w.y = (R)im;
+// FP64 -> storage word of P, one rounding to nearest even.
+template <typename P> __device__ __forceinline__ typename Word<P>::T cvt(double re, double im) {
+    typename Word<P>::T w;
+    w.x = static_cast<decltype(w.x)>(re);
+    w.y = static_cast<decltype(w.y)>(im);
     return w;
 }
 
@@ -212,23 +213,15 @@ __global__ void __launch_bounds__(kBlock) reduce_max_kernel(double* out, const d
     }
 }
 
-__global__ void __launch_bounds__(kBlock) narrow_kernel(float2* __restrict__ dst, const double2* __restrict__ src,
-                                                        int ncomp, Geo g) {
+template <typename P>
+__global__ void __launch_bounds__(kBlock) narrow_kernel(typename Word<P>::T* __restrict__ dst,
+                                                        const double2* __restrict__ src, int ncomp, double scale,
+                                                        Geo g) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.Vh) return;
     for (int c = 0; c < ncomp; ++c) {
         const double2 v = src[(int64_t)c * g.S + i];
-        dst[(int64_t)c * g.S + i] = make_float2((float)v.x, (float)v.y);
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) widen_kernel(double2* __restrict__ dst, const float2* __restrict__ src,
-                                                       int ncomp, Geo g) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= g.Vh) return;
-    for (int c = 0; c < ncomp; ++c) {
-        const float2 v = src[(int64_t)c * g.S + i];
-        dst[(int64_t)c * g.S + i] = make_double2((double)v.x, (double)v.y);
+        dst[(int64_t)c * g.S + i] = cvt<P>(scale * v.x, scale * v.y);
     }
 }
 
@@ -310,15 +303,11 @@ template hipError_t launch_gauge_export_r12<float>(double*, const float2*, const
 template hipError_t launch_compress_links<double>(double2*, const double2*, double*, const Geo&, hipStream_t);
 template hipError_t launch_compress_links<float>(float2*, const double2*, double*, const Geo&, hipStream_t);
 
-hipError_t launch_narrow(float2* dst, const double2* src, int ncomp, const Geo& g, hipStream_t s) {
+template <typename P>
+hipError_t launch_narrow(typename Word<P>::T* dst, const double2* src, int ncomp, double scale, const Geo& g,
+                         hipStream_t s) {
     if (g.Vh == 0) return hipSuccess;
-    hipLaunchKernelGGL(narrow_kernel, dim3(nblocks(g.Vh)), dim3(kBlock), 0, s, dst, src, ncomp, g);
-    return hipGetLastError();
-}
-
-hipError_t launch_widen(double2* dst, const float2* src, int ncomp, const Geo& g, hipStream_t s) {
-    if (g.Vh == 0) return hipSuccess;
-    hipLaunchKernelGGL(widen_kernel, dim3(nblocks(g.Vh)), dim3(kBlock), 0, s, dst, src, ncomp, g);
+    hipLaunchKernelGGL((narrow_kernel<P>), dim3(nblocks(g.Vh)), dim3(kBlock), 0, s, dst, src, ncomp, scale, g);
     return hipGetLastError();
 }
 
@@ -330,5 +319,14 @@ template hipError_t launch_spinor_import<double>(double2*, const double*, const 
 template hipError_t launch_spinor_import<float>(float2*, const double*, const Geo&, hipStream_t);
 template hipError_t launch_spinor_export<double>(double*, const double2*, const Geo&, hipStream_t);
 template hipError_t launch_spinor_export<float>(double*, const float2*, const Geo&, hipStream_t);
+template hipError_t launch_gauge_import<half_t>(h2*, const double*, const Geo&, hipStream_t);
+template hipError_t launch_gauge_export<half_t>(double*, const h2*, const Geo&, hipStream_t);
+template hipError_t launch_spinor_import<half_t>(h2*, const double*, const Geo&, hipStream_t);
+template hipError_t launch_spinor_export<half_t>(double*, const h2*, const Geo&, hipStream_t);
+template hipError_t launch_gauge_import_r12<half_t>(h2*, const double*, const Geo&, hipStream_t);
+template hipError_t launch_gauge_export_r12<half_t>(double*, const h2*, const Geo&, hipStream_t);
+template hipError_t launch_compress_links<half_t>(h2*, const double2*, double*, const Geo&, hipStream_t);
+template hipError_t launch_narrow<float>(float2*, const double2*, int, double, const Geo&, hipStream_t);
+template hipError_t launch_narrow<half_t>(h2*, const double2*, int, double, const Geo&, hipStream_t);
 
 }  // namespace tmh

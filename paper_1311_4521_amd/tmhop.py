@@ -43,12 +43,14 @@ TMH_ERR_UNSUPPORTED = -7
 EO, OE = 0, 1
 # precision codes: spinor word and link storage (F64_R12 / F32_R12 keep each
 # link as its first two rows, the third rebuilt in the kernels; SU(3) only)
-F64, F32, F64_R12, F32_R12 = 0, 1, 2, 3
+# F16 / F16_R12: FP16 storage with FP32 arithmetic
+F64, F32, F64_R12, F32_R12, F16, F16_R12 = 0, 1, 2, 3, 4, 5
+PREC_NAMES = ("f64", "f32", "f64r12", "f32r12", "f16", "f16r12")
 _DIRS = {"eo": EO, "oe": OE, EO: EO, OE: OE}
-_PRECS = {"f64": F64, "f32": F32, "f64r12": F64_R12, "f32r12": F32_R12,
-          F64: F64, F32: F32, F64_R12: F64_R12, F32_R12: F32_R12}
-_DTYPE = {F64: torch.float64, F32: torch.float32, F64_R12: torch.float64, F32_R12: torch.float32}
-_LINK_COMPS = {F64: 9, F32: 9, F64_R12: 6, F32_R12: 6}
+_PRECS = {**{n: k for k, n in enumerate(PREC_NAMES)}, **{k: k for k in range(len(PREC_NAMES))}}
+_DTYPE = {F64: torch.float64, F32: torch.float32, F64_R12: torch.float64, F32_R12: torch.float32,
+          F16: torch.float16, F16_R12: torch.float16}
+_LINK_COMPS = {F64: 9, F32: 9, F64_R12: 6, F32_R12: 6, F16: 9, F16_R12: 6}
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -500,8 +502,8 @@ def stream_copy(lat: Lattice, dst, src):
     _check(_lib.tmh_stream_copy(lat.handle, dst.data_ptr(), src.data_ptr(), n), "tmh_stream_copy")
 
 
-PROFILE_KINDS = 16
-PROFILE_NAMES = [f"{p}_{m}" for p in ("f64", "f32", "f64r12", "f32r12")
+PROFILE_KINDS = 24
+PROFILE_NAMES = [f"{p}_{m}" for p in PREC_NAMES
                  for m in ("ainv_or_plain", "twist", "twist_norm", "twist_cg_update")]
 
 
