@@ -425,7 +425,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
-            "kernel": "hop_kernel<double,0> (A^-1 H_eo store)",
+            "kernel": "hop_kernel<double,0,0> (A^-1 H_eo store, 9-entry links)",
             "bytes_per_site": BYTES_PER_SITE_F64,
             "avg_us": round(hop_us, 2),
             "launches": n0,

@@ -26,7 +26,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HOP_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("hop.hip", "hop_body.h", "common.h", "kernels.h")]
-DOMINANT = "tmh::hop_kernel<double, 0>"
+DOMINANT = "tmh::hop_kernel<double, 0, 0>"
 COPY = "stream_copy_kernel"
 
 
