@@ -194,8 +194,12 @@ tmh_status tmh_cg_solve(tmh_lattice* lat, void* x, const void* b, const void* ga
  * lattices share each launch.  A batch member is one lattice with nrhs
  * FP64 fields stored back to back (field r at base + r * tmh_spinor_bytes).
  * Tile shapes (sites x right-hand sides per workgroup): 0 = 256x1, 1 = 128x2,
- * 2 = 64x4, 3 = 128x4, 4 = 64x12; -1 picks the autotuned shape of the handle
- * (tmh_autotune_mrhs) or a default. */
+ * 2 = 64x4, 3 = 128x4, 4 = 64x12, where each thread owns one (site, rhs) and
+ * the right-hand sides of a workgroup share links through the caches; and
+ * 5 = 128x2, 6 = 64x4, 7 = 128x4 with 2, 8 = 64x12, 9 = 128x6 with 3, and
+ * 10 = 64x12, 11 = 128x4 with 4 right-hand sides per thread, which applies
+ * each link it loads to all of them from registers.  -1 picks the autotuned
+ * shape of the handle (tmh_autotune_mrhs) or a default. */
 typedef struct {
     tmh_lattice* lat;      /* every member on the same device, distinct handles */
     int nrhs;              /* right-hand sides (>= 1) */

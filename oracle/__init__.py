@@ -37,11 +37,17 @@ _lib = None
 
 
 def lib():
+    """The loaded oracle library.  ORACLE_LIB, when set, names another build
+    of oracle.c to load instead (the mutation tests run the pins against
+    deliberately broken copies this way)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = ctypes.CDLL(_LIB)
+        path = os.environ.get("ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(path):
+                build()
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         I = ctypes.c_int
         D = ctypes.c_double

@@ -146,6 +146,12 @@ int default_xgroup(const tmh_lattice* l) {
     return best;
 }
 
+#ifndef TMH_SITE_PAD
+#define TMH_SITE_PAD 0
+#endif
+// Site stride of the component arrays: Vh rounded up to 64 sites, plus a pad.
+int64_t site_stride(int64_t vh) { return (vh + 63) / 64 * 64 + TMH_SITE_PAD; }
+
 size_t spinor_bytes(const tmh_lattice* l, tmh_prec p) { return (size_t)12 * l->g.S * word_bytes(p); }
 size_t gauge_bytes(const tmh_lattice* l, tmh_prec p) {
     return (size_t)8 * link_comps(p) * l->g.S * word_bytes(p);
@@ -586,7 +592,7 @@ tmh_status tmh_lattice_create(tmh_lattice** out, const int dims[4], int device, 
     }
     // every component array (S FP64 complexes) must stay below 4 GiB: the
     // kernels address it through 32-bit buffer offsets
-    if ((V / 2 + 63) / 64 * 64 * 16 >= ((int64_t)1 << 32)) return TMH_ERR_GEOMETRY;
+    if (site_stride(V / 2) * 16 >= ((int64_t)1 << 32)) return TMH_ERR_GEOMETRY;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TMH_ERR_HIP;
     DeviceGuard guard(device);
@@ -598,7 +604,7 @@ tmh_status tmh_lattice_create(tmh_lattice** out, const int dims[4], int device, 
     l->stream = (hipStream_t)hip_stream;
     for (int m = 0; m < 4; ++m) l->g.L[m] = dims[m];
     l->g.Vh = (int)(V / 2);
-    l->g.S = (int)((V / 2 + 63) / 64 * 64);
+    l->g.S = (int)site_stride(V / 2);
     for (auto& row : l->tuned)
         for (int& v : row) v = -1;
     l->xgroup = default_xgroup(l);
@@ -887,15 +893,14 @@ int default_shape(const tmh_lattice* l, int nrhs, tmh_prec prec) {
 }
 
 int hop_tiles(const Geo& g, int shape) {
-    int sw, ry;
-    tmh::batch_shape(shape, &sw, &ry);
+    int sw, ry, nr;
+    tmh::batch_shape(shape, &sw, &ry, &nr);
     return (g.Vh + 64 * sw - 1) / (64 * sw);
 }
 
 int hop_items(const Geo& g, int nrhs, int shape) {
-    int sw, ry;
-    tmh::batch_shape(shape, &sw, &ry);
-    return hop_tiles(g, shape) * ((nrhs + ry - 1) / ry);
+    const int per = tmh::batch_rhs_per_item(shape);
+    return hop_tiles(g, shape) * ((nrhs + per - 1) / per);
 }
 
 template <typename R>

@@ -4,9 +4,11 @@
 // A batch is a list of tasks, one per lattice, each with nrhs fields stored
 // one after another (field r of a task at base + r * fstride words).  The
 // work of a launch is a list of items, task after task; an item is a tile of
-// 64*SW sites of one lattice for a group of RY right-hand sides, so the RY
-// waves-groups of a workgroup read the same links for the same sites and
-// the second and later reads of each link come from L1/L2.  A fixed
+// 64*SW sites of one lattice for a group of RY * NR right-hand sides: the RY
+// wave groups of a workgroup read the same links for the same sites (the
+// second and later reads come from L1/L2), and each thread applies the links
+// it loads to NR right-hand sides from registers.  The groups of a tile are
+// consecutive items.  A fixed
 // (persistent) grid walks the items: XCD k takes one contiguous range of
 // items, its workgroups stride through it.
 //
@@ -22,11 +24,19 @@
 
 namespace tmh {
 
-void batch_shape(int shape, int* sw, int* ry) {
-    static const int SW[kNumShapes] = {4, 2, 1, 2, 1};
-    static const int RY[kNumShapes] = {1, 2, 4, 4, 12};
+void batch_shape(int shape, int* sw, int* ry, int* nr) {
+    static const int SW[kNumShapes] = {4, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2};
+    static const int RY[kNumShapes] = {1, 2, 4, 4, 12, 1, 2, 2, 4, 2, 3, 1};
+    static const int NR[kNumShapes] = {1, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4};
     *sw = SW[shape];
     *ry = RY[shape];
+    *nr = NR[shape];
+}
+
+int batch_rhs_per_item(int shape) {
+    int sw, ry, nr;
+    batch_shape(shape, &sw, &ry, &nr);
+    return ry * nr;
 }
 
 namespace {
@@ -52,30 +62,39 @@ template <typename Table> __device__ __forceinline__ int find_task(const Table& 
     return t;
 }
 
-template <typename R, int MODE, int SW, int RY, bool PIPE>
+template <typename R, int MODE, int SW, int RY, int NR, bool PIPE>
 __global__ void __launch_bounds__(64 * SW * RY) batch_hop_kernel(BatchHopTable<R> tasks, int nitems) {
     constexpr int NSL = 64 * SW;
     const int lane_site = threadIdx.x % NSL;
     const int slot = threadIdx.x / NSL;
-    __shared__ double red[SW * RY];
+    __shared__ double red[SW * RY * NR];
     const XcdRange xr = xcd_range(nitems);
     for (int it = xr.k; it < xr.count; it += xr.nper) {
         const int item = xr.start + it;
         const BatchHopTask<R>& T = tasks.t[find_task(tasks, item)];
         const int local = item - T.item0;
-        const int ngroups = (T.nrhs + RY - 1) / RY;
+        // tile major: the groups of right-hand sides of a tile are neighbours
+        // in the item list, so they run close in time and share the links
+        const int ngroups = (T.nrhs + RY * NR - 1) / (RY * NR);
         const int tile = local / ngroups;
-        const int rhs = (local - tile * ngroups) * RY + slot;
+        const int rhs0 = ((local - tile * ngroups) * RY + slot) * NR;
         const int i = tile * NSL + lane_site;
-        double nrm = 0.0;
-        const bool live = rhs < T.nrhs && !(T.flags && T.flags[2 * (T.sys0 + rhs)]);
+        const int nv = rhs0 < T.nrhs ? (T.nrhs - rhs0 < NR ? T.nrhs - rhs0 : NR) : 0;
+        unsigned live = 0;  // bit r: right-hand side rhs0 + r is computed and stored
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if (r < nv && !(T.flags && T.flags[2 * (T.sys0 + rhs0 + r)])) live |= 1u << r;
+        double nrm[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) nrm[r] = 0.0;
         if (live && i < T.g.Vh) {
             HopArgs<R> a;
-            a.in = T.in + rhs * T.fstride;
+            a.in = T.in + rhs0 * T.fstride;
             a.gout = T.gout;
             a.gin = T.gin;
             a.g = T.g;
             a.pout = T.pout;
+            a.lf = 0;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 a.ph_re[m] = T.ph_re[m];
@@ -83,42 +102,58 @@ __global__ void __launch_bounds__(64 * SW * RY) batch_hop_kernel(BatchHopTable<R
             }
             int c[4], lex;
             site_coords(T.g, i, T.pout, c, lex);
-            cx<R> acc[4][3];
+            cx<R> acc[NR][4][3];
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int r = 0; r < NR; ++r)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) acc[s][k] = mk<R>(0, 0);
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) acc[r][s][k] = mk<R>(0, 0);
             const SiteNb n = site_neighbours(T.g, c, lex);
-            // links are shared by the RY right-hand sides: cache them unless RY == 1
-            hop_site<R, PIPE, (RY == 1 ? kLinkAux : 0)>(acc, a, n, i);
+            // links shared by several right-hand sides are kept in the caches
+            // unless this thread is their only user
+            constexpr int LAUX = (RY == 1 && NR == 1) ? kLinkAux : 0;
+            if constexpr (NR == 1)
+                hop_site<R, PIPE, LAUX>(acc[0], a, n, i);
+            else
+                hop_site_nr<R, NR, LAUX>(acc, a, T.fstride, nv, n, i);
             const int S = T.g.S;
-            typename Word<R>::T* out = T.out + rhs * T.fstride;
-            const typename Word<R>::T* aux = T.aux + rhs * T.fstride;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const cx<R> cc = mk<R>(T.c_re[s >> 1], T.c_im[s >> 1]);
+            for (int r = 0; r < NR; ++r) {
+                if (!((live >> r) & 1u)) continue;
+                typename Word<R>::T* out = T.out + (rhs0 + r) * T.fstride;
+                const typename Word<R>::T* aux = T.aux + (rhs0 + r) * T.fstride;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const int64_t comp = (int64_t)(3 * s + k) * S;
-                    cx<R> o = cc * acc[s][k];
-                    if constexpr (MODE >= 1)
-                        o += mk<R>(T.d_re[s >> 1], T.d_im[s >> 1]) * bload<R, out_aux<R>()>(aux + comp, S, i);
-                    if constexpr (MODE == 2) nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
-                    bstore<R, out_aux<R>()>(out + comp, S, i, o);
+                for (int s = 0; s < 4; ++s) {
+                    const cx<R> cc = mk<R>(T.c_re[s >> 1], T.c_im[s >> 1]);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const int64_t comp = (int64_t)(3 * s + k) * S;
+                        cx<R> o = cc * acc[r][s][k];
+                        if constexpr (MODE >= 1)
+                            o += mk<R>(T.d_re[s >> 1], T.d_im[s >> 1]) *
+                                 bload<R, out_aux<R>()>(aux + comp, S, i);
+                        if constexpr (MODE == 2) nrm[r] += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+                        bstore<R, out_aux<R>()>(out + comp, S, i, o);
+                    }
                 }
             }
         }
         if constexpr (MODE == 2) {
             // per right-hand side: the SW waves of a slot sum their sites
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
-            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
-            __syncthreads();
-            if (lane_site == 0 && rhs < T.nrhs) {
-                double s = 0.0;
+            for (int r = 0; r < NR; ++r) {
+                double v = nrm[r];
 #pragma unroll
-                for (int w = 0; w < SW; ++w) s += red[slot * SW + w];
-                T.partial[(int64_t)(T.sys0 + rhs) * T.pstride + tile] = s;
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                if ((threadIdx.x & 63) == 0) red[(threadIdx.x >> 6) * NR + r] = v;
+            }
+            __syncthreads();
+            if (lane_site < NR && rhs0 + lane_site < T.nrhs) {
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < SW; ++w) v += red[(slot * SW + w) * NR + lane_site];
+                T.partial[(int64_t)(T.sys0 + rhs0 + lane_site) * T.pstride + tile] = v;
             }
             __syncthreads();
         }
@@ -254,10 +289,10 @@ __global__ void __launch_bounds__(kBlock) batch_scalar_kernel(BatchSysTable sys,
 
 // ------------------------------------------------------------------ launchers
 
-template <typename R, int MODE, int SW, int RY>
+template <typename R, int MODE, int SW, int RY, int NR = 1>
 static const void* batch_hop_fn() {
     constexpr bool pipe = false;  // the persistent loop leaves no room for two register sets
-    return reinterpret_cast<const void*>(&batch_hop_kernel<R, MODE, SW, RY, pipe>);
+    return reinterpret_cast<const void*>(&batch_hop_kernel<R, MODE, SW, RY, NR, pipe>);
 }
 
 template <typename R, int MODE>
@@ -267,7 +302,14 @@ static const void* batch_hop_sel(int shape) {
         case kShape2x2: return batch_hop_fn<R, MODE, 2, 2>();
         case kShape1x4: return batch_hop_fn<R, MODE, 1, 4>();
         case kShape2x4: return batch_hop_fn<R, MODE, 2, 4>();
-        default: return batch_hop_fn<R, MODE, 1, 12>();
+        case kShape1x12: return batch_hop_fn<R, MODE, 1, 12>();
+        case kShape2x1r2: return batch_hop_fn<R, MODE, 2, 1, 2>();
+        case kShape1x2r2: return batch_hop_fn<R, MODE, 1, 2, 2>();
+        case kShape2x2r2: return batch_hop_fn<R, MODE, 2, 2, 2>();
+        case kShape1x4r3: return batch_hop_fn<R, MODE, 1, 4, 3>();
+        case kShape2x2r3: return batch_hop_fn<R, MODE, 2, 2, 3>();
+        case kShape1x3r4: return batch_hop_fn<R, MODE, 1, 3, 4>();
+        default: return batch_hop_fn<R, MODE, 2, 1, 4>();
     }
 }
 
@@ -312,8 +354,8 @@ static int persistent_grid(const void* fn, int threads, int nitems) {
 template <typename R>
 hipError_t launch_batch_hop(const BatchHopTable<R>& tasks, int nitems, int shape, int mode, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
-    int sw, ry;
-    batch_shape(shape, &sw, &ry);
+    int sw, ry, nr;
+    batch_shape(shape, &sw, &ry, &nr);
     const int threads = 64 * sw * ry;
     const void* fn = batch_hop_kernel_ptr<R>(shape, mode);
     const int grid = persistent_grid(fn, threads, nitems);
@@ -356,8 +398,8 @@ hipError_t launch_batch_scalar(int op, int nsys, const BatchSysTable& sys, doubl
 int batch_vec_tiles(int Vh) { return (Vh + kVecTile - 1) / kVecTile; }
 
 void batch_prepare(int shape) {
-    int sw, ry;
-    batch_shape(shape, &sw, &ry);
+    int sw, ry, nr;
+    batch_shape(shape, &sw, &ry, &nr);
     for (int mode = 0; mode < 3; ++mode) {
         (void)resident_blocks(batch_hop_kernel_ptr<double>(shape, mode), 64 * sw * ry);
         (void)resident_blocks(batch_hop_kernel_ptr<float>(shape, mode), 64 * sw * ry);

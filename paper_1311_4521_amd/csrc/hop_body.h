@@ -248,4 +248,45 @@ __device__ __forceinline__ void hop_site(cx<real_t<P>> (&acc)[4][3], const HopAr
     }
 }
 
+// Multi-right-hand-side form: NR fields `fstride` words apart share every
+// link load.  Per term the link goes to registers once and is applied to the
+// NR neighbour spinors in turn; right-hand sides r >= nv are skipped.
+template <typename P, int T, int LAUX>
+__device__ __forceinline__ void load_t_link(TermData<real_t<P>>& d, const HopArgs<P>& a, const SiteNb& n, int i) {
+    constexpr int MU = T / 2;
+    const int S = a.g.S;
+    const typename Word<P>::T* link = (T % 2 == 0 ? a.gout : a.gin) + (int64_t)MU * 9 * S;
+    const int jl = T % 2 == 0 ? i : n.jn[T];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d.u[k / 3][k % 3] = bload<P, LAUX>(link + (int64_t)k * S, S, jl);
+}
+
+template <typename P, int T>
+__device__ __forceinline__ void load_t_psi(TermData<real_t<P>>& d, const typename Word<P>::T* in, int S,
+                                           const SiteNb& n) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d.psi[s][c] = bload<P>(in + (int64_t)(3 * s + c) * S, S, n.jn[T]);
+}
+
+template <typename P, int NR, int LAUX>
+__device__ __forceinline__ void hop_site_nr(cx<real_t<P>> (&acc)[NR][4][3], const HopArgs<P>& a, int64_t fstride,
+                                            int nv, const SiteNb& n, int i) {
+    using R = real_t<P>;
+    TermData<R> d;
+#define TMH_TERM_NR(T)                                              \
+    load_t_link<P, T, LAUX>(d, a, n, i);                            \
+    _Pragma("unroll") for (int r = 0; r < NR; ++r) {                \
+        if (r < nv) {                                               \
+            load_t_psi<P, T>(d, a.in + r * fstride, a.g.S, n);      \
+            add_t<P, T>(acc[r], d, a, n);                           \
+        }                                                           \
+        TMH_SCHED_FENCE();                                          \
+    }
+    TMH_TERM_NR(0) TMH_TERM_NR(1) TMH_TERM_NR(2) TMH_TERM_NR(3)
+    TMH_TERM_NR(4) TMH_TERM_NR(5) TMH_TERM_NR(6) TMH_TERM_NR(7)
+#undef TMH_TERM_NR
+}
+
 }  // namespace tmh

@@ -127,8 +127,25 @@ hipError_t launch_cg_init(double* scal, const double* partial, int n, int* flags
 // (batch.hip) A batch task is one lattice with nrhs fields stored back to
 // back; systems are numbered across tasks (sys0 = first system of a task),
 // CG scalars live at scal[sys * kNScal], flags at flags[2 * sys].
-enum BatchShapeId { kShape4x1 = 0, kShape2x2 = 1, kShape1x4 = 2, kShape2x4 = 3, kShape1x12 = 4, kNumShapes = 5 };
-void batch_shape(int shape, int* sites_waves, int* rhs_per_group);
+// A tile shape: SW waves of 64 sites x RY wave groups, each thread applying
+// every link it loads to NR right-hand sides (an item holds RY * NR of them).
+enum BatchShapeId {
+    kShape4x1 = 0,
+    kShape2x2 = 1,
+    kShape1x4 = 2,
+    kShape2x4 = 3,
+    kShape1x12 = 4,
+    kShape2x1r2 = 5,
+    kShape1x2r2 = 6,
+    kShape2x2r2 = 7,
+    kShape1x4r3 = 8,
+    kShape2x2r3 = 9,
+    kShape1x3r4 = 10,
+    kShape2x1r4 = 11,
+    kNumShapes = 12
+};
+void batch_shape(int shape, int* sites_waves, int* wave_groups, int* rhs_per_thread);
+int batch_rhs_per_item(int shape);
 
 template <typename R> struct BatchHopTask {
     typename Word<R>::T* out;
