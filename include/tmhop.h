@@ -308,8 +308,11 @@ tmh_status tmh_stream_copy(tmh_lattice* lat, void* dst, const void* src, size_t 
  * tmh_hop_apply, tmh_qtm_apply and tmh_cg_solve) is bracketed by two HIP
  * events on the handle's stream.  tmh_profile_enable(on) resets the totals.
  * tmh_profile_read waits for the recorded launches and returns, for one
- * kernel kind, the number of launches and their summed duration in ms since
- * the last reset.  Kinds: 4*prec + mode, where prec is the tmh_prec code of
+ * kernel kind, the number of launches that did work and the summed duration
+ * of all its launches in ms since the last reset.  (The CG enqueues its
+ * iterations 8 at a time; launches of iterations past convergence find the
+ * stop flag set and return at once.  They are not counted; their few
+ * microseconds each stay in the total.)  Kinds: 4*prec + mode, where prec is the tmh_prec code of
  * the launch (0..5: spinor precision and the link storage it reads; the
  * recursions of tmh_cg_solve report the copy they run on) and mode is 0 (plain hop, or hop with the A^-1 store), 1 (hop
  * with the gamma_5 [A in - .] epilogue), 2 (as 1, plus the fused norm), 3 (as

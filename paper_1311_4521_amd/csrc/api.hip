@@ -50,6 +50,7 @@ struct tmh_lattice {
     std::vector<EventPair> prof_free;
     double prof_ms[TMH_PROFILE_KINDS];
     long long prof_count[TMH_PROFILE_KINDS];
+    long long prof_skipped[TMH_PROFILE_KINDS];  // launches that found the CG done and returned at once
 };
 
 namespace {
@@ -393,7 +394,9 @@ tmh_status cg_recursion(tmh_lattice* l, void* x, void* r, void* p, void* v, void
     TMH_TRY_HIP(tmh::launch_copy<R>((W*)p, (const W*)r, l->g, l->stream));
     *iters = 0;
     if (max_iter <= 0) return TMH_OK;
+    int enqueued = 0;
     for (;;) {
+        enqueued += kChunk;
         for (int k = 0; k < kChunk; ++k) {
             // v = Qhat(+) p with |v|^2 = (p, A p)
             TMH_TRY(qtm_launch<R>(l, v, gauge, p, te, kappa, mu, theta, +1, l->partial, l->flags, lf));
@@ -407,6 +410,15 @@ tmh_status cg_recursion(tmh_lattice* l, void* x, void* r, void* p, void* v, void
         if (l->h_flags[0]) break;
     }
     *iters = l->h_flags[1];
+    if (l->prof_on) {
+        // iterations enqueued after convergence ran as empty launches: two
+        // A^-1 stores, one twist + norm and one twist + update each
+        const long long skipped = enqueued - *iters;
+        const int base = 4 * prec_code<R>(lf);
+        l->prof_skipped[base + 0] += 2 * skipped;
+        l->prof_skipped[base + 2] += skipped;
+        l->prof_skipped[base + 3] += skipped;
+    }
     return TMH_OK;
 }
 
@@ -1466,6 +1478,7 @@ tmh_status tmh_profile_enable(tmh_lattice* l, int on) {
     for (int k = 0; k < TMH_PROFILE_KINDS; ++k) {
         l->prof_ms[k] = 0.0;
         l->prof_count[k] = 0;
+        l->prof_skipped[k] = 0;
     }
     return TMH_OK;
 }
@@ -1475,7 +1488,7 @@ tmh_status tmh_profile_read(tmh_lattice* l, int kind, long long* launches, doubl
     if (kind < 0 || kind >= TMH_PROFILE_KINDS || !launches || !total_ms) return TMH_ERR_ARG;
     DeviceGuard guard(l->device);
     TMH_TRY(prof_flush(l));
-    *launches = l->prof_count[kind];
+    *launches = l->prof_count[kind] - l->prof_skipped[kind];
     *total_ms = l->prof_ms[kind];
     return TMH_OK;
 }

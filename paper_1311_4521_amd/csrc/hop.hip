@@ -104,13 +104,17 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<P> 
 
 int hop_blocks(const Geo& g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
 
+#ifndef TMH_HOP_LDS_PAD
+#define TMH_HOP_LDS_PAD 0
+#endif
 template <typename P, int LF>
 static hipError_t launch_hop_lf(const HopArgs<P>& a, int mode, int nb, hipStream_t stream) {
+    constexpr unsigned lds = TMH_HOP_LDS_PAD;
     switch (mode) {
-        case 0: hipLaunchKernelGGL((hop_kernel<P, 0, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
-        case 1: hipLaunchKernelGGL((hop_kernel<P, 1, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
-        case 2: hipLaunchKernelGGL((hop_kernel<P, 2, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
-        default: hipLaunchKernelGGL((hop_kernel<P, 3, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        case 0: hipLaunchKernelGGL((hop_kernel<P, 0, LF>), dim3(nb), dim3(kHopBlock), lds, stream, a); break;
+        case 1: hipLaunchKernelGGL((hop_kernel<P, 1, LF>), dim3(nb), dim3(kHopBlock), lds, stream, a); break;
+        case 2: hipLaunchKernelGGL((hop_kernel<P, 2, LF>), dim3(nb), dim3(kHopBlock), lds, stream, a); break;
+        default: hipLaunchKernelGGL((hop_kernel<P, 3, LF>), dim3(nb), dim3(kHopBlock), lds, stream, a); break;
     }
     return hipGetLastError();
 }

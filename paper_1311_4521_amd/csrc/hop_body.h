@@ -53,8 +53,14 @@ namespace tmh {
 
 // Cache policy of the link loads: each link is read once per application,
 // so a non-temporal hint keeps it from displacing neighbour spinors.
-constexpr int kLinkAux = TMH_HOP_NT_LINKS ? 2 : 0;
-template <typename P> constexpr int out_aux() { return (TMH_HOP_NT_STORE && sizeof(P) == 8) ? 2 : 0; }
+#ifndef TMH_LINK_POLICY
+#define TMH_LINK_POLICY 2
+#endif
+#ifndef TMH_OUT_POLICY
+#define TMH_OUT_POLICY 2
+#endif
+constexpr int kLinkAux = TMH_HOP_NT_LINKS ? TMH_LINK_POLICY : 0;
+template <typename P> constexpr int out_aux() { return (TMH_HOP_NT_STORE && sizeof(P) == 8) ? TMH_OUT_POLICY : 0; }
 constexpr int kHopBlock = TMH_HOP_BLOCK;
 static_assert(kHopBlock == kHopThreads, "the host sizes hop launches with kHopThreads");
 

@@ -95,15 +95,35 @@ def traffic(fetch_dir, write_dir, out_json, copy_bytes=None, sites=None):
 
 
 def stats(stats_csv, out_md):
+    """Per-kernel table from rocprofv3's kernel statistics.  When the kernel
+    trace of the same run sits beside it (``*_kernel_trace.csv``), the table
+    also gives the average over the dispatches that did work: a CG enqueues
+    its iterations 8 at a time, and dispatches of iterations past convergence
+    return at once (a few microseconds); a dispatch shorter than a tenth of
+    its kernel's median is counted as such an early exit."""
     with open(stats_csv) as fh:
         rows = list(csv.DictReader(fh))
-    lines = ["| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
-    for r in rows[:20]:
+    work = {}
+    trace = glob.glob(os.path.join(os.path.dirname(stats_csv), "*kernel_trace.csv"))
+    if trace:
+        durs = {}
+        with open(trace[0]) as fh:
+            for r in csv.DictReader(fh):
+                durs.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        for name, d in durs.items():
+            d = sorted(d)
+            med = d[len(d) // 2]
+            kept = [x for x in d if x >= 0.1 * med]
+            work[name] = (len(d) - len(kept), sum(kept) / len(kept) / 1e3)
+    lines = ["| kernel | calls | total ms | avg us | % | early exits | avg us of the rest |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows[:24]:
         name = r["Name"]
-        if len(name) > 70:
-            name = name[:67] + "..."
-        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
-                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+        short = name if len(name) <= 70 else name[:67] + "..."
+        ex, avg = work.get(name, (None, None))
+        lines.append(f"| `{short}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} | "
+                     f"{'' if ex is None else ex} | {'' if avg is None else f'{avg:.2f}'} |")
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
