@@ -377,6 +377,19 @@ tmh_status true_residual(tmh_lattice* l, void* r, const void* b, const void* x, 
     return TMH_OK;
 }
 
+// The first residual of a solve: r = b when the start vector is zero (the
+// usual case, which then needs no operator application), else b - A x.
+tmh_status initial_residual(tmh_lattice* l, void* r, const void* b, const void* x, void* v, void* q, void* te,
+                            const void* gauge, double kappa, double mu, const double theta[4], double bb,
+                            double* rr) {
+    double xx;
+    TMH_TRY(reduce_dot<double>(l, &xx, x, x));
+    if (xx != 0.0) return true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, rr);
+    TMH_TRY_HIP(tmh::launch_copy<double>((double2*)r, (const double2*)b, l->g, l->stream));
+    *rr = bb;
+    return TMH_OK;
+}
+
 // CG recursion on A x = r0 where x holds the start vector and r holds
 // r0 - A x.  Iterates until |r|^2 <= stop or max_iter; scalars stay on the
 // device, the host looks at the flags once every kChunk iterations.
@@ -507,7 +520,7 @@ tmh_status cg_fp64(tmh_lattice* l, void* x, const void* b, const void* gauge, do
     int lf;
     TMH_TRY(links64(l, gauge, r12, &gr, &lf));
     double rr;
-    TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
+    TMH_TRY(initial_residual(l, r, b, x, v, q, te, gauge, kappa, mu, theta, bb, &rr));
     int total = 0;
     for (int restart = 0;; ++restart) {
         *res = sqrt(rr / bb);
@@ -555,7 +568,7 @@ tmh_status cg_mixed(tmh_lattice* l, void* x, const void* b, const void* gauge, d
         return TMH_OK;
     }
     double rr;
-    TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
+    TMH_TRY(initial_residual(l, r, b, x, v, q, te, gauge, kappa, mu, theta, bb, &rr));
     int total = 0;
     for (int outer = 0;; ++outer) {
         *res = sqrt(rr / bb);
