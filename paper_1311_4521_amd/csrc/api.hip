@@ -225,7 +225,7 @@ hipError_t hop_launch(tmh_lattice* l, const HopArgs<R>& a, int mode) {
             return hipErrorUnknown;
         }
     }
-    e.kind = 4 * prec_code<R>(a.lf) + mode;
+    e.kind = 4 * prec_code<R>(a.lf) + (mode < 3 ? mode : 3);
     hipError_t err = hipEventRecord(e.start, l->stream);
     if (err == hipSuccess) err = tmh::launch_hop<R>(a, mode, l->stream);
     if (err == hipSuccess) err = hipEventRecord(e.stop, l->stream);
@@ -295,8 +295,8 @@ hipError_t force_launch(tmh_lattice* l, int pout, void* force, const void* gauge
 }
 
 // The second operator of a CG iteration: q = Qhat(-) v, never stored; the
-// last launch applies r -= alpha q, x += alpha p (alpha from the device
-// scalars) and writes the |r|^2 partials.
+// last launch applies r -= alpha q (alpha from the device scalars), with x
+// non-null also x += alpha p, and writes the |r|^2 partials.
 template <typename R>
 tmh_status qtm_update(tmh_lattice* l, void* x, void* r, const void* p, const void* gauge, const void* v, void* te,
                       double kappa, double mu, const double theta[4], double* partial, const int* done,
@@ -315,8 +315,8 @@ tmh_status qtm_update(tmh_lattice* l, void* x, void* r, const void* p, const voi
     b.done = done;
     b.aux = (const W*)v;
     b.partial = partial;
-    b.xio = (W*)x;
     b.rio = (W*)r;
+    b.xio = (W*)x;
     b.pin = (const W*)p;
     b.scal = l->scal;
     b.c_re[0] = (tmh::real_t<R>)(-kappa);
@@ -325,7 +325,7 @@ tmh_status qtm_update(tmh_lattice* l, void* x, void* r, const void* p, const voi
     b.d_im[0] = (tmh::real_t<R>)mt;
     b.d_re[1] = (tmh::real_t<R>)-1;
     b.d_im[1] = (tmh::real_t<R>)mt;
-    TMH_TRY_HIP(hop_launch<R>(l, b, 3));
+    TMH_TRY_HIP(hop_launch<R>(l, b, x ? 4 : 3));
     return TMH_OK;
 }
 
@@ -414,10 +414,21 @@ tmh_status cg_recursion(tmh_lattice* l, void* x, void* r, void* p, void* v, void
             // v = Qhat(+) p with |v|^2 = (p, A p)
             TMH_TRY(qtm_launch<R>(l, v, gauge, p, te, kappa, mu, theta, +1, l->partial, l->flags, lf));
             TMH_TRY_HIP(tmh::launch_cg_alpha<R>(l->scal, l->partial, nb_hop, l->flags, l->stream));
-            // q = Qhat(-) v = A p, fused with x += alpha p, r -= alpha q and |r|^2
-            TMH_TRY(qtm_update<R>(l, x, r, p, gauge, v, te, kappa, mu, theta, l->partial, l->flags, lf));
-            TMH_TRY_HIP(tmh::launch_cg_beta(l->scal, l->partial, nb_hop, l->flags, max_iter, l->stream));
-            TMH_TRY_HIP(tmh::launch_cg_p<R>((W*)p, (const W*)r, l->scal, l->g, l->flags, l->stream));
+            // q = Qhat(-) v = A p, fused with r -= alpha q and |r|^2.  The
+            // solution update x += alpha p goes with the last hop in FP64,
+            // with the direction update p = r + beta p in FP32 and FP16:
+            // measured, each is the faster placement for its precision.
+            if constexpr (sizeof(W) == 16) {
+                TMH_TRY(qtm_update<R>(l, x, r, p, gauge, v, te, kappa, mu, theta, l->partial, l->flags, lf));
+                TMH_TRY_HIP(tmh::launch_cg_beta(l->scal, l->partial, nb_hop, l->flags, max_iter, l->stream));
+                TMH_TRY_HIP(tmh::launch_cg_p<R>((W*)p, (const W*)r, l->scal, l->g, l->flags, l->stream));
+            } else {
+                TMH_TRY(qtm_update<R>(l, nullptr, r, nullptr, gauge, v, te, kappa, mu, theta, l->partial, l->flags,
+                                      lf));
+                TMH_TRY_HIP(tmh::launch_cg_beta(l->scal, l->partial, nb_hop, l->flags, max_iter, l->stream));
+                TMH_TRY_HIP(tmh::launch_cg_px<R>((W*)p, (W*)x, (const W*)r, l->scal, l->g, l->flags,
+                                                 enqueued - kChunk + k, l->stream));
+            }
         }
         TMH_TRY(read_scalars(l));
         if (l->h_flags[0]) break;

@@ -138,6 +138,36 @@ __global__ void __launch_bounds__(kBlock) cg_p_kernel(typename Word<R>::T* __res
     }
 }
 
+// End of CG iteration `it` (0-based): x += alpha p, then p = r + beta p.
+// Runs only if that iteration ran (flags[1] counts the iterations done), so
+// the iteration that reaches the stop criterion still updates x, and the
+// iterations enqueued after it return at once.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) cg_px_kernel(typename Word<R>::T* __restrict__ p,
+                                                       typename Word<R>::T* __restrict__ x,
+                                                       const typename Word<R>::T* __restrict__ r,
+                                                       const double* __restrict__ scal, Geo g, const int* flags,
+                                                       int it) {
+    if (flags[1] != it + 1) return;
+    const real_t<R> alpha = (real_t<R>)scal[kAlpha];
+    const real_t<R> beta = (real_t<R>)scal[kBeta];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < g.Vh; i += gridDim.x * kBlock) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const int64_t k = (int64_t)c * g.S + i;
+            auto pv = p[k];
+            auto xv = x[k];
+            const auto rv = r[k];
+            xv.x += alpha * pv.x;
+            xv.y += alpha * pv.y;
+            pv.x = rv.x + beta * pv.x;
+            pv.y = rv.y + beta * pv.y;
+            x[k] = xv;
+            p[k] = pv;
+        }
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kBlock) sub_norm_kernel(typename Word<R>::T* __restrict__ out,
                                                           const typename Word<R>::T* __restrict__ a,
@@ -294,6 +324,13 @@ hipError_t launch_cg_p(typename Word<R>::T* p, const typename Word<R>::T* r, con
 }
 
 template <typename R>
+hipError_t launch_cg_px(typename Word<R>::T* p, typename Word<R>::T* x, const typename Word<R>::T* r,
+                        const double* scal, const Geo& g, const int* flags, int it, hipStream_t s) {
+    hipLaunchKernelGGL((cg_px_kernel<R>), dim3(blas_blocks(g)), dim3(kBlock), 0, s, p, x, r, scal, g, flags, it);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_sub_norm(typename Word<R>::T* out, const typename Word<R>::T* a, const typename Word<R>::T* b,
                            double* partial, const Geo& g, hipStream_t s) {
     hipLaunchKernelGGL((sub_norm_kernel<R>), dim3(blas_blocks(g)), dim3(kBlock), 0, s, out, a, b, partial, g);
@@ -333,6 +370,8 @@ hipError_t launch_zero(typename Word<R>::T* dst, const Geo& g, hipStream_t s) {
                                         const double*, double*, const Geo&, const int*, hipStream_t);         \
     template hipError_t launch_cg_p<R>(Word<R>::T*, const Word<R>::T*, const double*, const Geo&, const int*, \
                                        hipStream_t);                                                         \
+    template hipError_t launch_cg_px<R>(Word<R>::T*, Word<R>::T*, const Word<R>::T*, const double*,           \
+                                        const Geo&, const int*, int, hipStream_t);                           \
     template hipError_t launch_sub_norm<R>(Word<R>::T*, const Word<R>::T*, const Word<R>::T*, double*,        \
                                            const Geo&, hipStream_t);                                         \
     template hipError_t launch_copy<R>(Word<R>::T*, const Word<R>::T*, const Geo&, hipStream_t);              \

@@ -14,9 +14,11 @@
 //   MODE 0  out_s = c_{s/2} acc_s                      plain H, or A^-1 H
 //   MODE 1  out_s = c_{s/2} acc_s + d_{s/2} aux_s       gamma_5 [A aux - H (.)]
 //   MODE 2  as MODE 1, plus the per-workgroup partial of |out|^2 (FP64)
-//   MODE 3  CG update fused into the last hop of an iteration: with
-//           q = MODE 1 result (kept in registers), r -= alpha q, x += alpha p
-//           and the per-workgroup partial of |r|^2; q is not stored
+//   MODE 3  CG residual update fused into the last hop of an iteration:
+//           with q = MODE 1 result (kept in registers), r -= alpha q and the
+//           per-workgroup partial of |r|^2; q is not stored (x is updated
+//           with the search direction at the end of the iteration)
+//   MODE 4  as MODE 3, plus x += alpha p
 #include "common.h"
 #include "kernels.h"
 
@@ -79,7 +81,7 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<P> 
         const SiteNb n = site_neighbours(a.g, c, lex);
         hop_site<P, kHopPipe<P>, kLinkAux, LF>(acc, a, n, i);
         const int S = a.g.S;
-        const R alpha = MODE == 3 ? (R)a.scal[kAlpha] : (R)0;
+        const R alpha = MODE >= 3 ? (R)a.scal[kAlpha] : (R)0;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const cx<R> cc = mk<R>(a.c_re[s >> 1], a.c_im[s >> 1]);
@@ -90,15 +92,16 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<P> 
                 if constexpr (MODE >= 1)
                     o += mk<R>(a.d_re[s >> 1], a.d_im[s >> 1]) * bload<P, out_aux<P>()>(a.aux + comp, S, i);
                 if constexpr (MODE == 2) nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
-                if constexpr (MODE == 3) {
+                if constexpr (MODE >= 3) {
                     cx<R> r = bload<P>(a.rio + comp, S, i);
-                    cx<R> x = bload<P>(a.xio + comp, S, i);
-                    const cx<R> p = bload<P>(a.pin + comp, S, i);
                     r -= alpha * o;
-                    x += alpha * p;
                     bstore<P>(a.rio + comp, S, i, r);
-                    bstore<P>(a.xio + comp, S, i, x);
                     nrm += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+                    if constexpr (MODE == 4) {
+                        cx<R> x = bload<P>(a.xio + comp, S, i);
+                        x += alpha * bload<P>(a.pin + comp, S, i);
+                        bstore<P>(a.xio + comp, S, i, x);
+                    }
                 } else {
                     bstore<P, out_aux<P>()>(a.out + comp, S, i, o);
                 }
@@ -123,7 +126,8 @@ static hipError_t launch_hop_lf(const HopArgs<P>& a, int mode, int nb, hipStream
         case 0: hipLaunchKernelGGL((hop_kernel<P, 0, LF>), dim3(nb), dim3(kHopBlock), lds, stream, a); break;
         case 1: hipLaunchKernelGGL((hop_kernel<P, 1, LF>), dim3(nb), dim3(kHopBlock), lds, stream, a); break;
         case 2: hipLaunchKernelGGL((hop_kernel<P, 2, LF>), dim3(nb), dim3(kHopBlock), lds, stream, a); break;
-        default: hipLaunchKernelGGL((hop_kernel<P, 3, LF>), dim3(nb), dim3(kHopBlock), lds, stream, a); break;
+        case 3: hipLaunchKernelGGL((hop_kernel<P, 3, LF>), dim3(nb), dim3(kHopBlock), lds, stream, a); break;
+        default: hipLaunchKernelGGL((hop_kernel<P, 4, LF>), dim3(nb), dim3(kHopBlock), lds, stream, a); break;
     }
     return hipGetLastError();
 }

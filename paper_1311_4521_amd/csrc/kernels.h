@@ -18,9 +18,9 @@ template <typename P> struct HopArgs {
     const typename Word<P>::T* gin;   // links U_mu(y) of the input parity
     const typename Word<P>::T* aux;   // MODE >= 1: field added at the output site
     double* partial;                  // MODE 2: per-workgroup |out|^2; MODE 3: |r|^2
-    typename Word<P>::T* xio;         // MODE 3: x += alpha p
-    typename Word<P>::T* rio;         // MODE 3: r -= alpha out (out itself is not stored)
-    const typename Word<P>::T* pin;   // MODE 3: p
+    typename Word<P>::T* rio;         // MODE 3, 4: r -= alpha out (out itself is not stored)
+    typename Word<P>::T* xio;         // MODE 4: x += alpha p
+    const typename Word<P>::T* pin;   // MODE 4: p
     const double* scal;               // MODE 3: alpha = scal[kAlpha]
     const int* done;                  // optional device flag: skip when set
     Geo g;
@@ -99,9 +99,14 @@ hipError_t launch_cg_xr(typename Word<R>::T* x, typename Word<R>::T* r, const ty
                         const int* flags, hipStream_t s);
 hipError_t launch_cg_beta(double* scal, const double* partial, int n, int* flags, int max_iter,
                           hipStream_t s);
+// p = r + beta p (skipped once the CG is done).
 template <typename R>
 hipError_t launch_cg_p(typename Word<R>::T* p, const typename Word<R>::T* r, const double* scal,
                        const Geo& g, const int* flags, hipStream_t s);
+// x += alpha p, p = r + beta p, if CG iteration `it` (0-based) ran.
+template <typename R>
+hipError_t launch_cg_px(typename Word<R>::T* p, typename Word<R>::T* x, const typename Word<R>::T* r,
+                        const double* scal, const Geo& g, const int* flags, int it, hipStream_t s);
 // out = a - b, with |out|^2 partials (true residual).
 template <typename R>
 hipError_t launch_sub_norm(typename Word<R>::T* out, const typename Word<R>::T* a,
