@@ -272,8 +272,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the lattice would shard)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(DESIGN.md describes how the lattice would shard)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch":
