@@ -1108,12 +1108,13 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* m, int nmem, double rel_to
     // task tables of every step
     tmh::BatchHopTable<double> H[8];  // 0..3: CG iteration; 4..7: true residual A x
     memset(H, 0, sizeof H);
-    tmh::BatchVecTable Vxr, Vp, Vsub, Vnb, Vcp;
-    memset(&Vxr, 0, sizeof Vxr);
+    tmh::BatchVecTable Vp, Vsub, Vnb, Vcp, Vnx, Vrb;
     memset(&Vp, 0, sizeof Vp);
     memset(&Vsub, 0, sizeof Vsub);
     memset(&Vnb, 0, sizeof Vnb);
     memset(&Vcp, 0, sizeof Vcp);
+    memset(&Vnx, 0, sizeof Vnx);
+    memset(&Vrb, 0, sizeof Vrb);
     for (int k = 0, s0 = 0; k < nmem; ++k) {
         tmh_lattice* l = m[k].lat;
         const int n = m[k].nrhs;
@@ -1130,6 +1131,12 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* m, int nmem, double rel_to
             t.partial = partial;
             t.pstride = pstride;
             t.flags = h < 4 ? flags : nullptr;
+            if (h == 3) {  // the iteration's last hop carries the CG update (q is not stored)
+                t.rio = (double2*)r;
+                t.xio = (double2*)x;
+                t.pin = (const double2*)p;
+                t.scal = scal;
+            }
             t.sys0 = s0;
             t.item0 = H[h].ntasks == 0 ? 0 : H[h].t[H[h].ntasks - 1].item0 + hop_items(m[k - 1].lat->g, m[k - 1].nrhs, shape);
             H[h].t[H[h].ntasks++] = t;
@@ -1153,11 +1160,12 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* m, int nmem, double rel_to
             u.d = (const double2*)d;
             T.t[T.ntasks++] = u;
         };
-        push(Vxr, x, r, p, q);
         push(Vp, p, nullptr, r, nullptr);
         push(Vsub, r, nullptr, b, q);
         push(Vnb, nullptr, nullptr, b, nullptr);
         push(Vcp, p, nullptr, r, nullptr);
+        push(Vnx, nullptr, nullptr, x, nullptr);
+        push(Vrb, r, nullptr, b, nullptr);
         items_vec += n * vt.ntile;
         items_hop += hop_items(l->g, n, shape);
         s0 += n;
@@ -1189,8 +1197,7 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* m, int nmem, double rel_to
         if ((e = tmh::launch_batch_scalar(0, nsys, systab, scal, flags, partial, pstride, tol2, budget, s)) != hipSuccess)
             return e;
         if ((e = tmh::launch_batch_hop<double>(H[2], items_hop, shape, 0, s)) != hipSuccess) return e;
-        if ((e = tmh::launch_batch_hop<double>(H[3], items_hop, shape, 1, s)) != hipSuccess) return e;
-        if ((e = tmh::launch_batch_vec(0, Vxr, items_vec, scal, flags, s)) != hipSuccess) return e;
+        if ((e = tmh::launch_batch_hop<double>(H[3], items_hop, shape, 3, s)) != hipSuccess) return e;
         if ((e = tmh::launch_batch_scalar(1, nsys, systab, scal, flags, partial, pstride, tol2, budget, s)) != hipSuccess)
             return e;
         return tmh::launch_batch_vec(1, Vp, items_vec, scal, flags, s);
@@ -1201,15 +1208,31 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* m, int nmem, double rel_to
     hipGraphExec_t exec = nullptr;
     int graph_budget = -1;
     do {
-        // |b|^2 per system
-        if (tmh::launch_batch_vec(3, Vnb, items_vec, scal, flags, s) != hipSuccess ||
+        // |x|^2 (into kNorm), then |b|^2 per system; the |b|^2 partials stay
+        // in place for the restart step when every start vector is zero
+        if (tmh::launch_batch_vec(3, Vnx, items_vec, scal, flags, s) != hipSuccess ||
+            tmh::launch_batch_scalar(2, nsys, systab, scal, flags, partial, pstride, tol2, max_iter, s) != hipSuccess ||
+            tmh::launch_batch_vec(3, Vnb, items_vec, scal, flags, s) != hipSuccess ||
             tmh::launch_batch_scalar(4, nsys, systab, scal, flags, partial, pstride, tol2, max_iter, s) != hipSuccess) {
             st = TMH_ERR_HIP;
             break;
         }
         if ((st = read_back()) != TMH_OK) break;
-        for (int k = 0; k < nsys; ++k) bb[k] = h_scal[k * tmh::kNScal + tmh::kBB];
-        if ((st = true_res()) != TMH_OK) break;
+        bool zero_start = true;
+        for (int k = 0; k < nsys; ++k) {
+            bb[k] = h_scal[k * tmh::kNScal + tmh::kBB];
+            if (h_scal[k * tmh::kNScal + tmh::kNorm] != 0.0) zero_start = false;
+        }
+        if (zero_start) {
+            // r = b needs no operator application
+            if (tmh::launch_batch_vec(4, Vrb, items_vec, scal, flags, s) != hipSuccess) {
+                st = TMH_ERR_HIP;
+                break;
+            }
+            for (int k = 0; k < nsys; ++k) h_scal[k * tmh::kNScal + tmh::kNorm] = bb[k];
+        } else if ((st = true_res()) != TMH_OK) {
+            break;
+        }
         int it_done = 0;
         for (int restart = 0;; ++restart) {
             bool all = true;

@@ -121,8 +121,10 @@ __global__ void __launch_bounds__(64 * SW * RY) batch_hop_kernel(BatchHopTable<R
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (!((live >> r) & 1u)) continue;
-                typename Word<R>::T* out = T.out + (rhs0 + r) * T.fstride;
-                const typename Word<R>::T* aux = T.aux + (rhs0 + r) * T.fstride;
+                const int64_t fo = (rhs0 + r) * T.fstride;
+                typename Word<R>::T* out = T.out + fo;
+                const typename Word<R>::T* aux = T.aux + fo;
+                const R alpha = MODE == 3 ? (R)T.scal[(int64_t)(T.sys0 + rhs0 + r) * kNScal + kAlpha] : (R)0;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const cx<R> cc = mk<R>(T.c_re[s >> 1], T.c_im[s >> 1]);
@@ -134,12 +136,23 @@ __global__ void __launch_bounds__(64 * SW * RY) batch_hop_kernel(BatchHopTable<R
                             o += mk<R>(T.d_re[s >> 1], T.d_im[s >> 1]) *
                                  bload<R, out_aux<R>()>(aux + comp, S, i);
                         if constexpr (MODE == 2) nrm[r] += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
-                        bstore<R, out_aux<R>()>(out + comp, S, i, o);
+                        if constexpr (MODE == 3) {
+                            // the CG update: r -= alpha q, x += alpha p, |r|^2
+                            cx<R> rv = bload<R>(T.rio + fo + comp, S, i);
+                            rv -= alpha * o;
+                            bstore<R>(T.rio + fo + comp, S, i, rv);
+                            cx<R> xv = bload<R>(T.xio + fo + comp, S, i);
+                            xv += alpha * bload<R>(T.pin + fo + comp, S, i);
+                            bstore<R>(T.xio + fo + comp, S, i, xv);
+                            nrm[r] += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+                        } else {
+                            bstore<R, out_aux<R>()>(out + comp, S, i, o);
+                        }
                     }
                 }
             }
         }
-        if constexpr (MODE == 2) {
+        if constexpr (MODE >= 2) {
             // per right-hand side: the SW waves of a slot sum their sites
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -248,7 +261,7 @@ __device__ __forceinline__ double sys_sum(const double* __restrict__ partial, in
 }
 
 // op 0 (alpha): pq = sum(hop partials), alpha = rr / pq
-// op 1 (beta):  rr' = sum(vec partials), beta = rr'/rr, rr = rr', iterations, done
+// op 1 (beta):  rr' = sum(hop partials of the fused update), beta = rr'/rr, rr = rr', iterations, done
 // op 2 (norm):  scal[kNorm] = sum(vec partials)
 // op 3 (init):  rr = sum(vec partials); stop = tol^2 scal[kBB]; done = rr <= stop; iterations = 0
 // op 4 (bb):    scal[kBB] = sum(vec partials)
@@ -260,7 +273,7 @@ __global__ void __launch_bounds__(kBlock) batch_scalar_kernel(BatchSysTable sys,
     if ((OP == 0 || OP == 1) && flags[2 * s]) return;
     int t = 0;
     while (t + 1 < sys.ntasks && sys.sys0[t + 1] <= s) ++t;
-    const int n = OP == 0 ? sys.ntile_hop[t] : sys.ntile_vec[t];
+    const int n = (OP == 0 || OP == 1) ? sys.ntile_hop[t] : sys.ntile_vec[t];
     const double v = sys_sum(partial, pstride, s, n);
     if (threadIdx.x != 0) return;
     double* sc = scal + (int64_t)s * kNScal;
@@ -315,8 +328,12 @@ static const void* batch_hop_sel(int shape) {
 
 template <typename R>
 static const void* batch_hop_kernel_ptr(int shape, int mode) {
-    return mode == 0 ? batch_hop_sel<R, 0>(shape) : (mode == 1 ? batch_hop_sel<R, 1>(shape)
-                                                                : batch_hop_sel<R, 2>(shape));
+    switch (mode) {
+        case 0: return batch_hop_sel<R, 0>(shape);
+        case 1: return batch_hop_sel<R, 1>(shape);
+        case 2: return batch_hop_sel<R, 2>(shape);
+        default: return batch_hop_sel<R, 3>(shape);
+    }
 }
 
 // Workgroups of `fn` the device holds at once (CUs x resident workgroups per
@@ -400,7 +417,7 @@ int batch_vec_tiles(int Vh) { return (Vh + kVecTile - 1) / kVecTile; }
 void batch_prepare(int shape) {
     int sw, ry, nr;
     batch_shape(shape, &sw, &ry, &nr);
-    for (int mode = 0; mode < 3; ++mode) {
+    for (int mode = 0; mode < 4; ++mode) {
         (void)resident_blocks(batch_hop_kernel_ptr<double>(shape, mode), 64 * sw * ry);
         (void)resident_blocks(batch_hop_kernel_ptr<float>(shape, mode), 64 * sw * ry);
     }

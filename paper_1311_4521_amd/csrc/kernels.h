@@ -158,8 +158,12 @@ template <typename R> struct BatchHopTask {
     const typename Word<R>::T* aux;
     const typename Word<R>::T* gout;
     const typename Word<R>::T* gin;
-    double* partial;       // MODE 2: partial[sys * pstride + tile]
+    double* partial;       // MODE 2, 3: partial[sys * pstride + tile]
     const int* flags;      // optional: skip system when flags[2 * sys] != 0
+    typename Word<R>::T* rio;            // MODE 3: r -= alpha q (q not stored)
+    typename Word<R>::T* xio;            // MODE 3: x += alpha p
+    const typename Word<R>::T* pin;      // MODE 3: p
+    const double* scal;                  // MODE 3: alpha = scal[sys * kNScal + kAlpha]
     int64_t fstride;       // words between the fields of consecutive right-hand sides
     int64_t pstride;
     Geo g;
@@ -197,7 +201,7 @@ int batch_vec_tiles(int Vh);
 void batch_prepare(int shape);
 
 // Partial-sum counts per task: systems sys0 .. sys0 + nrhs - 1 of task k sum
-// ntile_hop partials after a MODE 2 hop and ntile_vec after a vector kernel.
+// ntile_hop partials after a MODE 2 or 3 hop and ntile_vec after a vector kernel.
 struct BatchSysTable {
     int sys0[kMaxBatchTasks], nrhs[kMaxBatchTasks], ntile_hop[kMaxBatchTasks], ntile_vec[kMaxBatchTasks];
     int ntasks;

@@ -99,6 +99,28 @@ def test_batch_graph_replays_match_eager():
             assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("use_graph", [False, True], ids=["eager", "graph"])
+def test_batch_nonzero_start(use_graph):
+    """A start vector that is not zero in one system takes the true-residual
+    path for the whole batch: restarting from the solutions takes no
+    iterations, and a perturbed start converges again to the oracle's
+    solution."""
+    members, host_data, kappa, mu = batch_problem()
+    it, res, ok = tm.batch_cg_solve(members, 1e-10, 2000, -1, use_graph)
+    assert ok
+    it2, res2, ok2 = tm.batch_cg_solve(members, 1e-10, 2000, -1, use_graph)
+    assert ok2 and max(it2) == 0 and res2 == res
+    for m in members:
+        m["x"].zero_()
+    members[1]["x"][2].fill_(0.5)       # one system starts elsewhere
+    it3, res3, ok3 = tm.batch_cg_solve(members, 1e-10, 2000, -1, use_graph)
+    assert ok3 and max(res3) <= 1e-10
+    dims, U, bs = host_data[1]
+    x = host(tm.spinor_export(members[1]["lat"], members[1]["x"][2]))
+    rr = bs[2] - oracle.normal(dims, U, x, kappa, mu, THETA_AP)
+    assert np.linalg.norm(rr) / np.linalg.norm(bs[2]) <= 1.05e-10
+
+
 def test_batch_not_converged_reported():
     members, _, _, _ = batch_problem()
     it, res, ok = tm.batch_cg_solve(members, 1e-10, 3, -1, True)
