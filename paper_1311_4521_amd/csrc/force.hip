@@ -20,9 +20,18 @@ namespace tmh {
 
 namespace {
 
+// Links and force entries are each touched by one thread once: their loads
+// and stores carry the non-temporal hint, which keeps them from displacing
+// the spinors, which four threads read.
+constexpr int kOnce = 2;
+
+// Grid: 2 * nb workgroups, remapped so that each XCD owns one contiguous
+// range of (parity, site block) pairs: both parities of a range of sites
+// and their neighbours then share that XCD's L2.
 __global__ void __launch_bounds__(kBlock) force_kernel(ForceArgs a) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    const int p = blockIdx.y;  // parity of the link sites handled by this grid row
+    const int vb = xcd_remap(blockIdx.x, gridDim.x);
+    const int p = vb & 1;       // parity of the link sites of this workgroup
+    const int i = (vb >> 1) * kBlock + threadIdx.x;
     if (i >= a.g.Vh) return;
     int c[4], lex;
     site_coords(a.g, i, p, c, lex);
@@ -107,7 +116,7 @@ __global__ void __launch_bounds__(kBlock) force_kernel(ForceArgs a) {
         if (a.kind == 0) {
             cx<double> u[3][3];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) u[k / 3][k % 3] = bload<double>(lk + (int64_t)k * S, S, i);
+            for (int k = 0; k < 9; ++k) u[k / 3][k % 3] = bload<double, kOnce>(lk + (int64_t)k * S, S, i);
             cx<double> M[3][3];
 #pragma unroll
             for (int r = 0; r < 3; ++r)
@@ -140,9 +149,9 @@ __global__ void __launch_bounds__(kBlock) force_kernel(ForceArgs a) {
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const cx<double> f = bload<double>(fo + (int64_t)k * S, S, i);
+            const cx<double> f = bload<double, kOnce>(fo + (int64_t)k * S, S, i);
             const cx<double> o = out[k / 3][k % 3];
-            bstore<double>(fo + (int64_t)k * S, S, i, mk<double>(f.re + a.coeff * o.re, f.im + a.coeff * o.im));
+            bstore<double, kOnce>(fo + (int64_t)k * S, S, i, mk<double>(f.re + a.coeff * o.re, f.im + a.coeff * o.im));
         }
     }
 }
@@ -152,7 +161,7 @@ __global__ void __launch_bounds__(kBlock) force_kernel(ForceArgs a) {
 hipError_t launch_force(const ForceArgs& a, hipStream_t s) {
     const int nb = (a.g.Vh + kBlock - 1) / kBlock;
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(force_kernel, dim3(nb, 2), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(force_kernel, dim3(2 * nb), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
