@@ -80,14 +80,67 @@ def cpu_baseline(dims, U, psi, kappa, theta, budget_s):
     for _ in range(reps):
         oracle.hop(dims, "eo", U, psi, kappa, theta)
     dt = time.perf_counter() - t0
+    cores = oracle.num_threads()
+    # the same sample on one thread, bounded to a few applications
+    oracle.set_num_threads(1)
+    try:
+        reps1 = max(1, min(reps, int(0.25 * budget_s / max(one * cores, 1e-9))))
+        t0 = time.perf_counter()
+        for _ in range(reps1):
+            oracle.hop(dims, "eo", U, psi, kappa, theta)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
     return {
         "value": round(FLOP_PER_SITE * Vh * reps / dt / 1e9, 3),
         "unit": "GFlop/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"{reps} oracle D_eo applications on the {'x'.join(map(str, dims))} fields "
                   f"({Vh} output sites each, {dt:.1f} s)",
+        "value_1_thread": round(FLOP_PER_SITE * Vh * reps1 / dt1 / 1e9, 3),
+        "sample_1_thread": f"{reps1} applications on one thread ({dt1:.1f} s)",
     }
+
+
+def hop_standalone(tm, lat, G, x, kappa, mu, theta, warm=10, reps=100):
+    """Single hopping-matrix applications outside the solver: D_eo and D_oe
+    on the resident FP64 fields, and one Q-hat+ application; each launch
+    timed on its own with HIP events on the library's stream.  Median and
+    minimum in us, with the algorithmic bandwidth at each."""
+    import torch
+    Vh = lat.Vh
+    out = lat.new_spinor()
+    res = {}
+
+    def stats(us, nbytes):
+        us = sorted(us)
+        med = us[len(us) // 2] if len(us) % 2 else 0.5 * (us[len(us) // 2 - 1] + us[len(us) // 2])
+        d = {"median_us": round(med, 2), "min_us": round(us[0], 2)}
+        if nbytes:
+            d["median_GBs"] = round(nbytes / (med * 1e-6) / 1e9, 1)
+            d["min_GBs"] = round(nbytes / (us[0] * 1e-6) / 1e9, 1)
+        return d
+
+    def timed(fn):
+        for _ in range(warm):
+            fn()
+        evs = [_events() for _ in range(reps)]
+        for a, b in evs:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) * 1e3 for a, b in evs]
+
+    for d in ("eo", "oe"):
+        res["hop_" + d] = stats(timed(lambda: tm.hop_apply(lat, d, out, G, x, kappa, theta)),
+                                BYTES_PER_SITE_F64 * Vh)
+    q = lat.new_spinor()
+    res["qtm_plus"] = stats(timed(lambda: tm.qtm_apply(lat, q, G, x, kappa, mu, theta, +1)), None)
+    res["timing"] = f"{warm} untimed, then {reps} applications each timed with HIP events"
+    del out, q
+    return res
 
 
 def _events():
@@ -402,6 +455,8 @@ def main():
     mixed_f16 = time_solve(tm.F16, args.mixed_steps)
     mixed_f16_r12 = time_solve(tm.F16_R12, args.mixed_steps)
 
+    log("standalone hop and Qtm applications")
+    standalone = hop_standalone(tm, lat, G, tb, kappa, mu, theta)
     traffic = measured_traffic(Vh)
     line = {
         "metric": METRIC,
@@ -434,6 +489,7 @@ def main():
         },
         "hop_gflops": round(FLOP_PER_SITE * Vh / (hop_us * 1e-6) / 1e9, 1),
         "kernels": per_kind,
+        "standalone": standalone,
         "cg_fp64": {"ms": round(fp64_ms, 3), "iterations": iters[0], "true_rel_res": res64},
         "cg_mixed_f32": mixed,
         "cg_mixed_f32_r12": mixed_r12,

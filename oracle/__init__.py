@@ -65,6 +65,8 @@ def lib():
         L.orc_gamma.argtypes = [I, P]
         L.orc_gamma.restype = None
         L.orc_num_threads.restype = I
+        L.orc_set_num_threads.argtypes = [I]
+        L.orc_set_num_threads.restype = None
         for name in ("orc_hop", "orc_hop_sites", "orc_hop_full", "orc_eo_sites", "orc_qtm",
                      "orc_cg", "orc_hop_force", "orc_qtm_force", "orc_full_operator"):
             getattr(L, name).restype = I
@@ -96,6 +98,11 @@ def _check(st, what):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's parallel loops from now on."""
+    lib().orc_set_num_threads(int(n))
 
 
 def gamma(m: int) -> np.ndarray:

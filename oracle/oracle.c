@@ -616,3 +616,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Sets the thread count of the parallel loops that follow (n >= 1). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

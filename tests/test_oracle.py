@@ -336,3 +336,21 @@ def test_generators_are_deterministic():
     b = fieldgen.gauge_haar((2, 2, 2, 2), 7)
     assert np.array_equal(a, b)
     assert np.array_equal(fieldgen.spinor_gauss(10, 3), fieldgen.spinor_gauss(10, 3))
+
+
+def test_thread_count_does_not_change_results():
+    """Each output site is computed by one thread from the inputs alone, so
+    the hop is bitwise the same on one thread and on all of them."""
+    dims = (4, 6, 2, 6)
+    U = fieldgen.gauge_haar(dims, 61)
+    psi = fieldgen.spinor_gauss(int(np.prod(dims)) // 2, 62)
+    n = oracle.num_threads()
+    try:
+        oracle.set_num_threads(1)
+        assert oracle.num_threads() == 1
+        one = oracle.hop(dims, "eo", U, psi, 0.16, (1.0, 0.3, 0.0, 0.0))
+    finally:
+        oracle.set_num_threads(n)
+    assert oracle.num_threads() == n
+    many = oracle.hop(dims, "eo", U, psi, 0.16, (1.0, 0.3, 0.0, 0.0))
+    assert np.array_equal(one, many)
