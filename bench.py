@@ -326,7 +326,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
-              "(DESIGN.md describes how the lattice would shard)", file=sys.stderr)
+              "(the lattice would be split along T, then Z, one process per GPU)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch":

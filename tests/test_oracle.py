@@ -1,7 +1,8 @@
 """Pins of the CPU oracle against facts that do not come from the oracle.
 
 * closed forms: the free-field (U = 1) plane-wave symbol of the hopping term
-  and the free-field eigenvalue of Qhat^dagger Qhat (derived in the design doc);
+  and the free-field eigenvalue of Qhat^dagger Qhat (derived at
+  ``free_lambda``);
 * invariants: gauge covariance under random SU(3) transformations,
   gamma_5-hermiticity of the hopping term, Qhat(+)^dagger = Qhat(-);
 * brute force: dense matrices built independently in ``tests/dense.py`` on
@@ -260,7 +261,16 @@ def test_cg_matches_dense_solve():
 # ------------------------------------------------------- free-field Qtm/CG
 
 def free_lambda(p, kappa, mt):
-    """Eigenvalue of Mhat^dagger Mhat on a free plane wave of momentum p."""
+    """Eigenvalue of Mhat^dagger Mhat on a free plane wave of momentum p.
+
+    On the wave both hops act as K = a - i B with a = 2 kappa sum cos p_mu
+    and B = 2 kappa sum gamma_mu sin p_mu, B^2 = s2 = 4 kappa^2 sum sin^2 p_mu.
+    With A = 1 + i mt gamma_5, A^-1 = (1 - i mt gamma_5) / D, D = 1 + mt^2,
+    and gamma_5 B = -B gamma_5:
+    K A^-1 K = [(a^2 - s2) - 2 i a B - i mt (a^2 + s2) gamma_5] / D, so
+    Mhat = A - K A^-1 K = alpha + i beta gamma_5 + i (2a / D) B with the
+    alpha, beta below; in Mhat^dagger Mhat the cross terms in
+    gamma_5 B + B gamma_5 vanish, leaving alpha^2 + beta^2 + (2a / D)^2 s2."""
     a = 2 * kappa * np.sum(np.cos(p))
     s2 = 4 * kappa ** 2 * np.sum(np.sin(p) ** 2)
     D = 1 + mt ** 2
