@@ -46,8 +46,9 @@ WORKLOADS = {
     # the mixed-precision workload: smoothed links U = exp(i 0.3 H); the
     # paper's 48^3x96 inversion fixes no kappa or mu, the 32^3x64 values are reused
     "mixed48": dict(dims=(96, 48, 48, 48), kappa=0.1632, mt=0.0013, seed=3, links="smooth",
-                    label="FP64 CG vs FP32-inner defect-correction CG to 1e-10 on 48^3x96, "
-                          "links exp(0.3 i H), kappa=0.1632, 2*kappa*mu=0.0013, antiperiodic time"),
+                    label="FP64 CG vs defect-correction CG (FP32 or FP16-storage inner) to 1e-10 "
+                          "on 48^3x96, links exp(0.3 i H), kappa=0.1632, 2*kappa*mu=0.0013, "
+                          "antiperiodic time"),
 }
 
 
