@@ -167,12 +167,14 @@ tmh_status tmh_qtm_apply(tmh_lattice* lat, void* out, const void* gauge, const v
  *   inner = TMH_F32: defect correction -- the FP64 outer loop forms the true
  *           residual, updates x and does every global reduction in FP64 on
  *           the device; each inner solve runs CG with the FP32 hopping matrix
- *           on an FP32 copy of the links made inside this call.
+ *           on an FP32 copy of the links made inside this call, on the
+ *           residual scaled to unit mean square per real component (so the
+ *           source's magnitude does not matter), and stops at a relative
+ *           residual no smaller than 1e-5.
  *   inner = TMH_F16: defect correction as TMH_F32, with every field of
  *           the inner CG stored in FP16 (arithmetic and reductions in FP32 /
- *           FP64).  Each inner solve takes the residual scaled to unit mean
- *           square per real component, so that its vectors stay in FP16's
- *           normal range, and stops at a relative residual no smaller than
+ *           FP64); the scaling keeps its vectors in FP16's normal range.
+ *           Each inner solve stops at a relative residual no smaller than
  *           3e-3; more outer steps replace the precision FP16 lacks.
  *   inner = TMH_F64_R12 / TMH_F32_R12 / TMH_F16_R12: as without _R12, but
  *           the CG recursion reads a two-row copy of the links made inside

@@ -554,9 +554,10 @@ tmh_status cg_fp64(tmh_lattice* l, void* x, const void* b, const void* gauge, do
 #endif
 template <typename P> constexpr double inner_tol_min() { return sizeof(P) == 4 ? 1e-5 : TMH_INNER_TOL_F16; }
 constexpr int kMaxOuter = 64;
-// The inner system is scaled: FP32 takes the residual as it is, FP16 takes
-// it scaled to unit mean square per real component (so that the recursion's
-// vectors stay inside FP16's normal range); the correction is scaled back.
+// The inner system is scaled: the residual enters the inner solve scaled to
+// unit mean square per real component, so that the recursion's vectors stay
+// inside the normal range of FP16 (from 6.1e-5) or FP32 (from 1.2e-38)
+// whatever the source's magnitude; the correction is scaled back.
 template <typename P>
 tmh_status cg_mixed(tmh_lattice* l, void* x, const void* b, const void* gauge, double kappa, double mu,
                     const double theta[4], double tol, int max_iter, int* iters, double* res, bool r12) {
@@ -587,7 +588,7 @@ tmh_status cg_mixed(tmh_lattice* l, void* x, const void* b, const void* gauge, d
         if (outer >= kMaxOuter || total >= max_iter || !(rr > 0.0)) break;
         double inner = 0.5 * tol / *res;
         if (inner < inner_tol_min<P>()) inner = inner_tol_min<P>();
-        const double scale = sizeof(P) == 4 ? 1.0 : sqrt(24.0 * l->g.Vh / rr);
+        const double scale = sqrt(24.0 * l->g.Vh / rr);
         TMH_TRY_HIP(tmh::launch_narrow<P>(rl, (const double2*)r, 12, scale, l->g, l->stream));
         TMH_TRY_HIP(tmh::launch_zero<P>(dl, l->g, l->stream));
         int it = 0;
