@@ -70,7 +70,9 @@ def measured_traffic(n_sites):
     return round(t.get("bytes_per_launch"), 0)
 
 
-def cpu_baseline(dims, U, psi, kappa, theta, budget_s):
+def cpu_baseline(dims, U, psi, kappa, theta, budget_s, cg=None):
+    import numpy as np
+
     import oracle
     Vh = len(psi)
     t0 = time.perf_counter()
@@ -85,14 +87,14 @@ def cpu_baseline(dims, U, psi, kappa, theta, budget_s):
     # the same sample on one thread, bounded to a few applications
     oracle.set_num_threads(1)
     try:
-        reps1 = max(1, min(reps, int(0.25 * budget_s / max(one * cores, 1e-9))))
+        reps1 = max(3, min(reps, int(0.25 * budget_s / max(one * cores, 1e-9))))
         t0 = time.perf_counter()
         for _ in range(reps1):
             oracle.hop(dims, "eo", U, psi, kappa, theta)
         dt1 = time.perf_counter() - t0
     finally:
         oracle.set_num_threads(cores)
-    return {
+    out = {
         "value": round(FLOP_PER_SITE * Vh * reps / dt / 1e9, 3),
         "unit": "GFlop/s",
         "cores": cores,
@@ -102,6 +104,17 @@ def cpu_baseline(dims, U, psi, kappa, theta, budget_s):
         "value_1_thread": round(FLOP_PER_SITE * Vh * reps1 / dt1 / 1e9, 3),
         "sample_1_thread": f"{reps1} applications on one thread ({dt1:.1f} s)",
     }
+    if cg is not None:
+        # one full oracle CG of the benchmark system on all threads, and its
+        # solution against the GPU's FP64 one (both at true residual 1e-10)
+        mu, x_gpu = cg
+        t0 = time.perf_counter()
+        x, it, res, ok = oracle.cg(dims, U, psi, kappa, mu, theta, 1e-10, 20000)
+        dtc = time.perf_counter() - t0
+        out["cg"] = {"seconds": round(dtc, 2), "iterations": it, "true_rel_res": res, "converged": ok,
+                     "rel_diff_vs_gpu_fp64_solution":
+                         float(np.linalg.norm(x - x_gpu) / np.linalg.norm(x))}
+    return out
 
 
 def hop_standalone(tm, lat, G, x, kappa, mu, theta, warm=10, reps=100):
@@ -500,7 +513,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        line["cpu_baseline"] = cpu_baseline(dims, U, b, kappa, theta, args.cpu_seconds)
+        x_gpu = tm.spinor_export(lat, x64).cpu().numpy()
+        line["cpu_baseline"] = cpu_baseline(dims, U, b, kappa, theta, args.cpu_seconds, cg=(mu, x_gpu))
     print(json.dumps(line), flush=True)
     lat.close()
 

@@ -57,3 +57,24 @@ def test_source_magnitude(inner, s):
     # both solutions solve their systems to 1e-10, so they agree to about
     # cond * 1e-10; the condition number of this system is below 1e3
     assert np.linalg.norm(xs / s - x1) <= 1e-6 * np.linalg.norm(x1)
+
+
+@pytest.mark.parametrize("inner", CODES, ids=IDS.get)
+def test_iteration_cap(inner):
+    """With too few iterations allowed every code reports non-convergence,
+    stays within the cap and returns a finite true residual."""
+    U = haar(DIMS, 904)
+    b = gauss(np.prod(DIMS) // 2, 905)
+    x, it, res, ok = solve_capped(U, b, inner, 3)
+    assert not ok and 1 <= it <= 3
+    assert np.isfinite(res) and 1e-10 < res < 1.0
+    assert np.all(np.isfinite(x))
+    assert abs(oracle_res(U, x, b) - res) <= 1e-6 * res
+
+
+def solve_capped(U, b, inner, max_iter):
+    lat = tm.Lattice(DIMS)
+    G = tm.gauge_import(lat, U)
+    x = lat.new_spinor()
+    it, res, ok = tm.cg_solve(lat, x, tm.spinor_import(lat, b), G, KAPPA, MU, THETA_AP, 1e-10, max_iter, inner)
+    return tm.spinor_export(lat, x).cpu().numpy(), it, res, ok
