@@ -962,6 +962,27 @@ tmh::BatchHopTask<R> hop_task(const tmh_lattice* l, int pout, void* out, const v
     return t;
 }
 
+// Tile order of a batched hop task (batch.hip, tile_site): x-group order
+// where tiles fill whole (t, x) planes and T splits into 8 chunks, with the
+// largest group whose time-slice holds at most TMH_BATCH_XG_SITES
+// site-right-hand-side pairs (at least one x value); else even-odd order.
+#ifndef TMH_BATCH_XG_SITES
+#define TMH_BATCH_XG_SITES 8192
+#endif
+template <typename R> void batch_traversal(tmh::BatchHopTask<R>& t, const tmh_lattice* l, int shape) {
+    int sw, ry, nr;
+    tmh::batch_shape(shape, &sw, &ry, &nr);
+    const int nsl = 64 * sw, plane = l->dims[2] * l->dims[3] / 2;
+    t.xgroup = 0;
+    if (TMH_BATCH_XG_SITES <= 0 || plane % nsl != 0 || l->dims[0] % 8 != 0) return;
+    int best = 1;
+    for (int xg = 1; xg <= l->dims[1]; ++xg)
+        if (l->dims[1] % xg == 0 && (int64_t)xg * plane * t.nrhs <= TMH_BATCH_XG_SITES) best = xg;
+    t.xgroup = best;
+    t.nyt = plane / nsl;
+    t.nt = l->dims[0] / 8;
+}
+
 // Coefficients of the four hop steps of Qhat(sign): step 0 stores A^-1 H,
 // step 1 forms gamma_5 [A aux - H].
 template <typename R>
@@ -1036,6 +1057,7 @@ tmh_status tmh_hop_apply_mrhs(tmh_lattice* l, tmh_dir dir, void* out, const void
         tab.ntasks = 1;
         tab.t[0] = hop_task<double>(l, pout, out, gauge, in, nullptr, nrhs, theta);
         tab.t[0].c_re[0] = tab.t[0].c_re[1] = kappa;
+        batch_traversal(tab.t[0], l, shape);
         TMH_TRY_HIP(tmh::launch_batch_hop<double>(tab, items, shape, 0, l->stream));
     } else {
         tmh::BatchHopTable<float> tab;
@@ -1043,6 +1065,7 @@ tmh_status tmh_hop_apply_mrhs(tmh_lattice* l, tmh_dir dir, void* out, const void
         tab.ntasks = 1;
         tab.t[0] = hop_task<float>(l, pout, out, gauge, in, nullptr, nrhs, theta);
         tab.t[0].c_re[0] = tab.t[0].c_re[1] = (float)kappa;
+        batch_traversal(tab.t[0], l, shape);
         TMH_TRY_HIP(tmh::launch_batch_hop<float>(tab, items, shape, 0, l->stream));
     }
     return TMH_OK;
@@ -1129,6 +1152,7 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* m, int nmem, double rel_to
         for (int h = 0; h < 8; ++h) {
             auto t = hop_task<double>(l, h % 2 == 0 ? 0 : 1, out0[h], m[k].gauge, in0[h], aux0[h], n, m[k].theta);
             qtm_coeffs(t, h % 2, m[k].kappa, m[k].mu, signs[h]);
+            batch_traversal(t, l, shape);
             t.partial = partial;
             t.pstride = pstride;
             t.flags = h < 4 ? flags : nullptr;

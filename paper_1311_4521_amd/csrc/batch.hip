@@ -56,6 +56,29 @@ __device__ __forceinline__ XcdRange xcd_range(int nitems) {
     return r;
 }
 
+// First site of tile `tile` (nsl sites) of a task.  In x-group order the
+// lattice is cut into 8 chunks of nt time-slices (one per XCD when the batch
+// is one lattice); a chunk is visited x-group by x-group, each group over
+// all the chunk's slices for xgroup consecutive x values.  All the
+// right-hand sides of a tile are consecutive items, so the input one tile
+// needs is the tile's neighbourhood in every right-hand side; this order
+// brings the t neighbours of the tiles resident at one time closer than
+// even-odd order does (measured: 3 % faster at 32^3x64 with 12 right-hand
+// sides).
+__device__ __forceinline__ int tile_site(int tile, int nsl, int xgroup, int nyt, int nt, int LX) {
+    if (xgroup <= 0) return tile * nsl;
+    const int per_chunk = nt * LX * nyt;
+    const int chunk = tile / per_chunk;
+    int rem = tile - chunk * per_chunk;
+    const int per_group = nt * xgroup * nyt;
+    const int xg = rem / per_group;
+    rem -= xg * per_group;
+    const int tl = rem / (xgroup * nyt);
+    rem -= tl * (xgroup * nyt);
+    const int xi = rem / nyt, yb = rem - xi * nyt;
+    return (((chunk * nt + tl) * LX + xg * xgroup + xi) * nyt + yb) * nsl;
+}
+
 template <typename Table> __device__ __forceinline__ int find_task(const Table& tab, int item) {
     int t = 0;
     while (t + 1 < tab.ntasks && tab.t[t + 1].item0 <= item) ++t;
@@ -78,7 +101,7 @@ __global__ void __launch_bounds__(64 * SW * RY) batch_hop_kernel(BatchHopTable<R
         const int ngroups = (T.nrhs + RY * NR - 1) / (RY * NR);
         const int tile = local / ngroups;
         const int rhs0 = ((local - tile * ngroups) * RY + slot) * NR;
-        const int i = tile * NSL + lane_site;
+        const int i = tile_site(tile, NSL, T.xgroup, T.nyt, T.nt, T.g.L[1]) + lane_site;
         const int nv = rhs0 < T.nrhs ? (T.nrhs - rhs0 < NR ? T.nrhs - rhs0 : NR) : 0;
         unsigned live = 0;  // bit r: right-hand side rhs0 + r is computed and stored
 #pragma unroll

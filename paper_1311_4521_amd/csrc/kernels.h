@@ -168,6 +168,10 @@ template <typename R> struct BatchHopTask {
     int64_t pstride;
     Geo g;
     int pout, nrhs, sys0, item0;
+    // tile order: xgroup = 0 visits tiles in even-odd order; xgroup > 0
+    // visits each eighth of the time-slices (nt of them) x-group by x-group,
+    // nyt tiles filling one (t, x) plane
+    int xgroup, nyt, nt;
     R ph_re[4], ph_im[4], c_re[2], c_im[2], d_re[2], d_im[2];
 };
 constexpr int kMaxBatchTasks = 8;  // lattices per batch (task tables travel as kernel arguments)
