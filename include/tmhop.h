@@ -48,8 +48,9 @@
  *   gauge (whole lattice): element (a, b) of U_mu(x), x of parity p with
  *             even-odd index i, is the complex element ((p*4+mu)*9 + 3a+b)*S + i;
  *             tmh_gauge_bytes() = 72*S complexes.
- *   gauge, two-row storage (TMH_F64_R12, TMH_F32_R12): only rows a = 0, 1 are
- *             stored, element (a, b) at ((p*4+mu)*6 + 3a+b)*S + i,
+ *   gauge, two-row storage (TMH_F64_R12, TMH_F32_R12, TMH_F16_R12): only
+ *             rows a = 0, 1 are stored, element (a, b) at
+ *             ((p*4+mu)*6 + 3a+b)*S + i,
  *             tmh_gauge_bytes() = 48*S complexes.  The kernels rebuild row 2
  *             as the complex conjugate of the cross product of rows 0 and 1,
  *             which is exact for special unitary links (a unitary matrix with
@@ -135,8 +136,8 @@ size_t tmh_site_stride(const tmh_lattice* lat);
 size_t tmh_spinor_bytes(const tmh_lattice* lat, tmh_prec prec);
 size_t tmh_gauge_bytes(const tmh_lattice* lat, tmh_prec prec);
 
-/* Canonical FP64 -> internal layout in precision `prec` (rounded to nearest
- * for FP32), and back.  src and dst are device buffers and must not overlap
+/* Canonical FP64 -> internal layout in precision `prec` (rounded once, to
+ * nearest even, for FP32 and FP16), and back.  src and dst are device buffers and must not overlap
  * (TMH_ERR_ALIAS).  Two-row gauge import keeps rows 0 and 1 of each link and
  * export rebuilds row 2 from them. */
 tmh_status tmh_gauge_import(tmh_lattice* lat, void* dst, const double* src, tmh_prec prec);
@@ -314,11 +315,13 @@ tmh_status tmh_stream_copy(tmh_lattice* lat, void* dst, const void* src, size_t 
  * of all its launches in ms since the last reset.  (The CG enqueues its
  * iterations 8 at a time; launches of iterations past convergence find the
  * stop flag set and return at once.  They are not counted; their few
- * microseconds each stay in the total.)  Kinds: 4*prec + mode, where prec is the tmh_prec code of
- * the launch (0..5: spinor precision and the link storage it reads; the
- * recursions of tmh_cg_solve report the copy they run on) and mode is 0 (plain hop, or hop with the A^-1 store), 1 (hop
- * with the gamma_5 [A in - .] epilogue), 2 (as 1, plus the fused norm), 3 (as
- * 1, with the CG update r -= alpha q, x += alpha p and |r|^2 fused in). */
+ * microseconds each stay in the total.)  Kinds: 4*prec + mode, where prec
+ * is the tmh_prec code of the launch (0..5: spinor precision and the link
+ * storage it reads; the recursions of tmh_cg_solve report the copy they run
+ * on) and mode is 0 (plain hop, or hop with the A^-1 store), 1 (hop with
+ * the gamma_5 [A in - .] epilogue), 2 (as 1, plus the fused norm), 3 (as 1,
+ * with the CG update fused in: r -= alpha q and |r|^2, and in the FP64
+ * recursion also x += alpha p). */
 #define TMH_PROFILE_KINDS 24
 tmh_status tmh_profile_enable(tmh_lattice* lat, int on);
 tmh_status tmh_profile_read(tmh_lattice* lat, int kind, long long* launches, double* total_ms);
