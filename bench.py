@@ -337,6 +337,8 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-standalone", action="store_true",
+                    help="skip the standalone hop/Qtm timings (profiling runs: they launch the same kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -469,8 +471,10 @@ def main():
     mixed_f16 = time_solve(tm.F16, args.mixed_steps)
     mixed_f16_r12 = time_solve(tm.F16_R12, args.mixed_steps)
 
-    log("standalone hop and Qtm applications")
-    standalone = hop_standalone(tm, lat, G, tb, kappa, mu, theta)
+    standalone = None
+    if not args.no_standalone:
+        log("standalone hop and Qtm applications")
+        standalone = hop_standalone(tm, lat, G, tb, kappa, mu, theta)
     traffic = measured_traffic(Vh)
     line = {
         "metric": METRIC,
