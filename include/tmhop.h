@@ -120,11 +120,17 @@ tmh_status tmh_lattice_set_stream(tmh_lattice* lat, void* hip_stream);
  * contiguous range of time-slices; with xgroup > 0 it visits that range
  * x-group by x-group (all its time-slices for xgroup consecutive x values,
  * then the next group), which keeps the neighbours of the sites in flight
- * within fewer L2 lines.  0 = even-odd order.  The default is the largest
- * xgroup with xgroup * LY * LZ / 2 <= 8192 when the geometry tiles (LY*LZ/2 a
- * multiple of 64, T a multiple of 8, xgroup divides LX); tmh_autotune_hop
- * measures instead.  TMH_ERR_UNSUPPORTED if the geometry does not tile for
- * this xgroup.  tmh_lattice_traversal returns the current value. */
+ * within fewer L2 lines.  0 = even-odd order.  TMH_TRAVERSAL_XSLAB splits x
+ * instead of t among the 8 XCDs: XCD k owns x in [k LX/8, (k+1) LX/8) over
+ * all time-slices and sweeps t, so that neighbouring XCDs read their shared
+ * x boundaries at about the same time (needs LX a multiple of 8).  The
+ * default is the largest xgroup with xgroup * LY * LZ / 2 <= 8192 when the
+ * geometry tiles (LY*LZ/2 a multiple of 64, T a multiple of 8, xgroup
+ * divides LX, V/2 a multiple of 2048); tmh_autotune_hop measures every
+ * order instead.  TMH_ERR_UNSUPPORTED if the geometry does not tile for this
+ * order, TMH_ERR_ARG for other negative values.  tmh_lattice_traversal
+ * returns the current value (-1 for a null handle). */
+#define TMH_TRAVERSAL_XSLAB (-8)
 tmh_status tmh_lattice_set_traversal(tmh_lattice* lat, int xgroup);
 int tmh_lattice_traversal(const tmh_lattice* lat);
 
@@ -240,9 +246,9 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* members, int nmembers, dou
 tmh_status tmh_autotune_mrhs(tmh_lattice* lat, const void* gauge, int nrhs, tmh_prec prec,
                              const char* cache_path, int* best_shape, double* best_us);
 
-/* Autotuner of the hop traversal: times tmh_hop_apply for xgroup = 0 and
- * every valid group on this lattice, keeps the fastest in the handle and
- * returns it.  With cache_path, a line "<arch> <T>x<LX>x<LY>x<LZ> <prec> hop
+/* Autotuner of the hop traversal: times tmh_hop_apply for xgroup = 0,
+ * TMH_TRAVERSAL_XSLAB and every valid group on this lattice, keeps the
+ * fastest in the handle and returns it.  With cache_path, a line "<arch> <T>x<LX>x<LY>x<LZ> <prec> hop
  * <xgroup> <us>" (prec one of f64, f32, f64r12, f32r12, f16, f16r12; gauge
  * in that storage) is looked up first and appended after timing.  Blocks. */
 tmh_status tmh_autotune_hop(tmh_lattice* lat, const void* gauge, tmh_prec prec,

@@ -130,10 +130,15 @@ tmh_status ensure(void** p, size_t bytes) {
 // The x-group traversal of the hop kernel applies when the geometry tiles
 // exactly: 64-site units fill whole (t, x) planes, every XCD owns whole
 // time-slices and a whole number of workgroups, and the group divides LX.
+// The x-slab traversal needs whole planes, LX a multiple of 8 and a whole
+// number of workgroups per XCD.
+static_assert(tmh::kXSlab == TMH_TRAVERSAL_XSLAB, "the kernels and the ABI name the x-slab order alike");
 bool xgroup_ok(const tmh_lattice* l, int xg) {
     const int plane = l->dims[2] * l->dims[3] / 2;
-    return xg > 0 && plane % 64 == 0 && l->dims[0] % 8 == 0 && l->dims[1] % xg == 0 &&
-           l->g.Vh % (64 * 8) == 0 && (l->g.Vh / 64 / 8) % (tmh::kHopThreads / 64) == 0;
+    const bool tiles = plane % 64 == 0 && l->g.Vh % (64 * 8) == 0 &&
+                       (l->g.Vh / 64 / 8) % (tmh::kHopThreads / 64) == 0;
+    if (xg == tmh::kXSlab) return tiles && l->dims[1] % 8 == 0;
+    return xg > 0 && tiles && l->dims[0] % 8 == 0 && l->dims[1] % xg == 0;
 }
 
 // Default: the largest group of x values whose sites (xg LY LZ / 2 per
@@ -692,8 +697,8 @@ void tmh_lattice_destroy(tmh_lattice* l) {
 
 tmh_status tmh_lattice_set_traversal(tmh_lattice* l, int xgroup) {
     TMH_TRY(check_lat(l));
-    if (xgroup < 0) return TMH_ERR_ARG;
-    if (xgroup > 0 && !xgroup_ok(l, xgroup)) return TMH_ERR_UNSUPPORTED;
+    if (xgroup < 0 && xgroup != TMH_TRAVERSAL_XSLAB) return TMH_ERR_ARG;
+    if (xgroup != 0 && !xgroup_ok(l, xgroup)) return TMH_ERR_UNSUPPORTED;
     l->xgroup = xgroup;
     return TMH_OK;
 }
@@ -1467,8 +1472,12 @@ tmh_status tmh_autotune_hop(tmh_lattice* l, const void* gauge, tmh_prec prec, co
     if (hipMemsetAsync(in, 0, sb, l->stream) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
         hipEventCreate(&e1) != hipSuccess)
         st = TMH_ERR_HIP;
-    for (int xg = 0; xg <= l->dims[1] && st == TMH_OK; ++xg) {
-        if (xg > 0 && !xgroup_ok(l, xg)) continue;
+    std::vector<int> cands = {0};
+    if (xgroup_ok(l, tmh::kXSlab)) cands.push_back(tmh::kXSlab);
+    for (int xg = 1; xg <= l->dims[1]; ++xg)
+        if (xgroup_ok(l, xg)) cands.push_back(xg);
+    for (size_t ci = 0; ci < cands.size() && st == TMH_OK; ++ci) {
+        const int xg = cands[ci];
         l->xgroup = xg;
         for (int w = 0; w < 2 && st == TMH_OK; ++w) st = tmh_hop_apply(l, TMH_EO, out, gauge, in, 0.1, theta, prec);
         const int reps = 5;

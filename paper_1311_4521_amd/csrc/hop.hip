@@ -33,12 +33,23 @@ namespace tmh {
 // 64-site units (one wave each) x-group by x-group: all the XCD's
 // time-slices for xgroup consecutive x values, then the next group.  The
 // sites resident at one time, and their neighbours, then form a more compact
-// region than in slice-by-slice order.  nyb units fill one (t, x) plane.
-// Returns the first site of the unit handled by wave w of hardware block b.
+// region than in slice-by-slice order.  With xgroup = kXSlab the XCDs split
+// x instead: XCD k owns x in [k LX/8, (k+1) LX/8) over all time-slices and
+// sweeps t, so that all XCDs reach their shared x boundaries at the same
+// time.  nyb units fill one (t, x) plane.  Returns the first site of the
+// unit handled by wave w of hardware block b.
 __device__ __forceinline__ int unit_site(int b, int w, int nb, int xgroup, int nyb, int nt, int LX) {
 #if TMH_XCD_REMAP
     const int q = nb / kXcds, r = nb % kXcds;
     const int xc = b % kXcds, k = b / kXcds;
+    if (xgroup == kXSlab) {
+        constexpr int W = kHopBlock / 64;
+        const int u = k * W + w;
+        const int xw = LX / kXcds, per_t = xw * nyb;
+        const int tl = u / per_t, rem = u - tl * per_t;
+        const int xi = rem / nyb, yb = rem - xi * nyb;
+        return ((tl * LX + xc * xw + xi) * nyb + yb) * 64;
+    }
     if (xgroup > 0) {
         constexpr int W = kHopBlock / 64;
         const int u = k * W + w;  // unit rank inside the XCD's range

@@ -8,6 +8,9 @@
 
 namespace tmh {
 
+// Traversal code of the hop kernels for one x-slab per XCD (see hop.hip).
+constexpr int kXSlab = -8;
+
 // Arguments of one hopping-matrix launch on fields of storage precision P
 // (double, float or half_t), arithmetic in real_t<P>.
 template <typename P> struct HopArgs {

@@ -41,6 +41,7 @@ TMH_ERR_NOT_CONVERGED = -6
 TMH_ERR_UNSUPPORTED = -7
 
 EO, OE = 0, 1
+XSLAB = -8  # traversal: one x-slab per XCD (TMH_TRAVERSAL_XSLAB)
 # precision codes: spinor word and link storage (F64_R12 / F32_R12 keep each
 # link as its first two rows, the third rebuilt in the kernels; SU(3) only)
 # F16 / F16_R12: FP16 storage with FP32 arithmetic
@@ -184,7 +185,8 @@ class Lattice:
 
     @property
     def traversal(self) -> int:
-        """x values per traversal group of the hop kernels (0: even-odd order)."""
+        """x values per traversal group of the hop kernels (0: even-odd
+        order; XSLAB: one x-slab per XCD)."""
         return int(_lib.tmh_lattice_traversal(self.handle))
 
     @traversal.setter

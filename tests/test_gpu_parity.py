@@ -329,7 +329,9 @@ def test_traversal_orders_agree():
     first = {}
     with pytest.raises(tm.TmhError):
         lat.traversal = 3          # does not divide LX
-    for xg in (0, 1, 2, 4, 8):
+    with pytest.raises(tm.TmhError):
+        lat.traversal = -2         # no such order
+    for xg in (0, 1, 2, 4, 8, tm.XSLAB):
         lat.traversal = xg
         assert lat.traversal == xg
         for d in ("eo", "oe"):
@@ -351,7 +353,7 @@ def test_autotune_hop_cache(tmp_path):
     G = tm.gauge_import(lat, haar(dims, 611))
     cache = str(tmp_path / "hop.txt")
     xg, us = tm.autotune_hop(lat, G, tm.F64, cache)
-    assert xg in (0, 1, 2, 4, 8) and us > 0 and lat.traversal == xg
+    assert xg in (0, 1, 2, 4, 8, tm.XSLAB) and us > 0 and lat.traversal == xg
     words = open(cache).read().split()
     assert words[1:4] == ["8x8x8x16", "f64", "hop"] and int(words[4]) == xg
     lat2 = tm.Lattice(dims)

@@ -105,7 +105,7 @@ def test_traversals_agree_with_two_row_links():
     x = tm.spinor_import(lat, psi, tm.F64_R12)
     ref = oracle.hop(dims, "oe", U, psi, kappa, THETA_AP)
     first = None
-    for xg in (0, 1, 2, 4, 8):
+    for xg in (0, 1, 2, 4, 8, tm.XSLAB):
         lat.traversal = xg
         out = lat.new_spinor(tm.F64_R12)
         tm.hop_apply(lat, "oe", out, G, x, kappa, THETA_AP, tm.F64_R12)
