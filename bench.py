@@ -375,9 +375,17 @@ def main():
     G = tm.gauge_import(lat, U)
     tb = tm.spinor_import(lat, b)
     x = lat.new_spinor()
+    by_code = {}
     if args.xgroup is None:
+        # every storage code the solves below launch gets its own traversal
+        for prec in (tm.F32, tm.F32_R12, tm.F64_R12, tm.F16, tm.F16_R12):
+            Gp = tm.gauge_import(lat, U, prec)
+            by_code[tmhop.PREC_NAMES[prec]] = tm.autotune_hop(lat, Gp, prec)[0]
+            del Gp
         xgroup, tuned_us = tm.autotune_hop(lat, G, tm.F64)
-        log(f"fields resident on the device; hop traversal x-group {xgroup} ({tuned_us:.1f} us, autotuned)")
+        by_code["f64"] = xgroup
+        log(f"fields resident on the device; hop traversal x-group {xgroup} ({tuned_us:.1f} us, autotuned); "
+            f"per storage code {by_code}")
     else:
         lat.traversal = xgroup = args.xgroup
         log(f"fields resident on the device; hop traversal x-group {xgroup} (fixed)")
@@ -490,7 +498,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w["label"], "dims_TXYZ": list(dims), "kappa": kappa,
-                   "two_kappa_mu": mt, "tol": 1e-10, "seed": w["seed"], "hop_traversal_xgroup": xgroup},
+                   "two_kappa_mu": mt, "tol": 1e-10, "seed": w["seed"], "hop_traversal_xgroup": xgroup,
+                   "hop_traversal_by_code": by_code or None},
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),

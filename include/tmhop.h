@@ -246,9 +246,12 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* members, int nmembers, dou
 tmh_status tmh_autotune_mrhs(tmh_lattice* lat, const void* gauge, int nrhs, tmh_prec prec,
                              const char* cache_path, int* best_shape, double* best_us);
 
-/* Autotuner of the hop traversal: times tmh_hop_apply for xgroup = 0,
- * TMH_TRAVERSAL_XSLAB and every valid group on this lattice, keeps the
- * fastest in the handle and returns it.  With cache_path, a line "<arch> <T>x<LX>x<LY>x<LZ> <prec> hop
+/* Autotuner of the hop traversal: times tmh_hop_apply in precision prec for
+ * xgroup = 0, TMH_TRAVERSAL_XSLAB and every valid group on this lattice and
+ * returns the fastest.  The handle keeps it for every later launch of that
+ * storage code (hop, qtm and the CG recursions, including the inner solves
+ * of tmh_cg_solve) and as its order for the codes not tuned;
+ * tmh_lattice_set_traversal discards the per-code choices.  With cache_path, a line "<arch> <T>x<LX>x<LY>x<LZ> <prec> hop
  * <xgroup> <us>" (prec one of f64, f32, f64r12, f32r12, f16, f16r12; gauge
  * in that storage) is looked up first and appended after timing.  Blocks. */
 tmh_status tmh_autotune_hop(tmh_lattice* lat, const void* gauge, tmh_prec prec,

@@ -36,6 +36,8 @@ struct tmh_lattice {
     int mrhs_cap;           // right-hand sides mrhs[] can hold
     int tuned[2][17];       // autotuned batch tile shape per (precision, nrhs <= 16), -1: none
     int xgroup;             // hop traversal: x values per group (0: even-odd order)
+    bool xtuned[6];         // traversal tuned for launches of one storage code ...
+    int xgroup_code[6];     // ... and its value (tmh_autotune_hop)
     double2* v64[4];        // FP64 CG vectors r, p, v, q
     void* vlow[2][5];       // inner CG vectors r, p, v, q, d of the mixed solve: [0] FP32, [1] FP16
     void* glow[2];          // FP32 / FP16 copy of the links for the mixed-precision inner solve
@@ -185,8 +187,10 @@ HopArgs<R> hop_args(const tmh_lattice* l, int pout, void* out, const void* gauge
     a.g = l->g;
     a.pout = pout;
     a.lf = lf;
-    if (xgroup_ok(l, l->xgroup)) {
-        a.xgroup = l->xgroup;
+    const int code = prec_code<R>(lf);
+    const int xg = l->xtuned[code] ? l->xgroup_code[code] : l->xgroup;
+    if (xgroup_ok(l, xg)) {
+        a.xgroup = xg;
         a.nyb = l->dims[2] * l->dims[3] / 2 / 64;
         a.nt = l->dims[0] / 8;
     }
@@ -700,6 +704,7 @@ tmh_status tmh_lattice_set_traversal(tmh_lattice* l, int xgroup) {
     if (xgroup < 0 && xgroup != TMH_TRAVERSAL_XSLAB) return TMH_ERR_ARG;
     if (xgroup != 0 && !xgroup_ok(l, xgroup)) return TMH_ERR_UNSUPPORTED;
     l->xgroup = xgroup;
+    for (bool& t : l->xtuned) t = false;  // an explicit order applies to every code
     return TMH_OK;
 }
 
@@ -1449,8 +1454,10 @@ tmh_status tmh_autotune_hop(tmh_lattice* l, const void* gauge, tmh_prec prec, co
                 }
             }
             fclose(f);
-            if (xg >= 0) {
+            if (xg != -1) {
                 l->xgroup = xg;
+                l->xtuned[prec] = true;
+                l->xgroup_code[prec] = xg;
                 *best_xgroup = xg;
                 *best_us = us;
                 return TMH_OK;
@@ -1468,7 +1475,9 @@ tmh_status tmh_autotune_hop(tmh_lattice* l, const void* gauge, tmh_prec prec, co
     const double theta[4] = {1.0, 0.0, 0.0, 0.0};
     double best = 1e300;
     int bx = 0;
-    const int saved = l->xgroup;
+    const int saved = l->xgroup, saved_code = l->xgroup_code[prec];
+    const bool saved_tuned = l->xtuned[prec];
+    l->xtuned[prec] = true;
     if (hipMemsetAsync(in, 0, sb, l->stream) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
         hipEventCreate(&e1) != hipSuccess)
         st = TMH_ERR_HIP;
@@ -1476,23 +1485,33 @@ tmh_status tmh_autotune_hop(tmh_lattice* l, const void* gauge, tmh_prec prec, co
     if (xgroup_ok(l, tmh::kXSlab)) cands.push_back(tmh::kXSlab);
     for (int xg = 1; xg <= l->dims[1]; ++xg)
         if (xgroup_ok(l, xg)) cands.push_back(xg);
-    for (size_t ci = 0; ci < cands.size() && st == TMH_OK; ++ci) {
-        const int xg = cands[ci];
-        l->xgroup = xg;
-        for (int w = 0; w < 2 && st == TMH_OK; ++w) st = tmh_hop_apply(l, TMH_EO, out, gauge, in, 0.1, theta, prec);
-        const int reps = 5;
-        if (st == TMH_OK && hipEventRecord(e0, l->stream) != hipSuccess) st = TMH_ERR_HIP;
-        for (int k = 0; k < reps && st == TMH_OK; ++k)
-            st = tmh_hop_apply(l, k % 2 ? TMH_OE : TMH_EO, out, gauge, in, 0.1, theta, prec);
-        float ms = 0.f;
-        if (st == TMH_OK && (hipEventRecord(e1, l->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            st = TMH_ERR_HIP;
-        if (st == TMH_OK && 1e3 * ms / reps < best) {
-            best = 1e3 * ms / reps;
-            bx = xg;
+    // two rounds over the candidates, each candidate's time the smaller of
+    // its two, so that a drift of the clock or of other load during one
+    // round does not decide between orders a few per cent apart
+    std::vector<double> cand_us(cands.size(), 1e300);
+    for (int round = 0; round < 2 && st == TMH_OK; ++round) {
+        for (size_t ci = 0; ci < cands.size() && st == TMH_OK; ++ci) {
+            const int xg = cands[ci];
+            l->xgroup = xg;
+            l->xgroup_code[prec] = xg;
+            for (int w = 0; w < 2 && st == TMH_OK; ++w)
+                st = tmh_hop_apply(l, TMH_EO, out, gauge, in, 0.1, theta, prec);
+            const int reps = 6;
+            if (st == TMH_OK && hipEventRecord(e0, l->stream) != hipSuccess) st = TMH_ERR_HIP;
+            for (int k = 0; k < reps && st == TMH_OK; ++k)
+                st = tmh_hop_apply(l, k % 2 ? TMH_OE : TMH_EO, out, gauge, in, 0.1, theta, prec);
+            float ms = 0.f;
+            if (st == TMH_OK && (hipEventRecord(e1, l->stream) != hipSuccess ||
+                                 hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = TMH_ERR_HIP;
+            if (st == TMH_OK) cand_us[ci] = std::min(cand_us[ci], 1e3 * ms / reps);
         }
     }
+    for (size_t ci = 0; ci < cands.size(); ++ci)
+        if (cand_us[ci] < best) {
+            best = cand_us[ci];
+            bx = cands[ci];
+        }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(l->stream);
@@ -1500,9 +1519,12 @@ tmh_status tmh_autotune_hop(tmh_lattice* l, const void* gauge, tmh_prec prec, co
     (void)hipFree(out);
     if (st != TMH_OK) {
         l->xgroup = saved;
+        l->xgroup_code[prec] = saved_code;
+        l->xtuned[prec] = saved_tuned;
         return st;
     }
     l->xgroup = bx;
+    l->xgroup_code[prec] = bx;
     *best_xgroup = bx;
     *best_us = best;
     if (cache_path) {

@@ -358,3 +358,32 @@ def test_autotune_hop_cache(tmp_path):
     assert words[1:4] == ["8x8x8x16", "f64", "hop"] and int(words[4]) == xg
     lat2 = tm.Lattice(dims)
     assert tm.autotune_hop(lat2, tm.gauge_import(lat2, haar(dims, 611)), tm.F64, cache) == (xg, float(words[5]))
+    # a cached x-slab order is read back as such
+    cache2 = str(tmp_path / "hop2.txt")
+    with open(cache2, "w") as fh:
+        fh.write(f"{words[0]} 8x8x8x16 f64 hop {tm.XSLAB} 1.5\n")
+    lat3 = tm.Lattice(dims)
+    assert tm.autotune_hop(lat3, tm.gauge_import(lat3, haar(dims, 611)), tm.F64, cache2) == (tm.XSLAB, 1.5)
+    assert lat3.traversal == tm.XSLAB
+
+
+def test_traversal_tuned_per_storage_code():
+    """Tuning one storage code leaves the others' choice in place, and every
+    code still matches the oracle whatever its order."""
+    dims, kappa = (8, 8, 8, 16), 0.1632
+    U = haar(dims, 621)
+    psi = gauss(int(np.prod(dims)) // 2, 622)
+    lat = tm.Lattice(dims)
+    G64 = tm.gauge_import(lat, U)
+    G16 = tm.gauge_import(lat, U, tm.F16_R12)
+    xg64, _ = tm.autotune_hop(lat, G64, tm.F64)
+    xg16, _ = tm.autotune_hop(lat, G16, tm.F16_R12)
+    assert lat.traversal == xg16
+    ref = oracle.hop(dims, "eo", U, psi, kappa, THETA_AP)
+    out = lat.new_spinor()
+    tm.hop_apply(lat, "eo", out, G64, tm.spinor_import(lat, psi), kappa, THETA_AP)
+    assert site_rel_err(to_host(tm.spinor_export(lat, out)), ref) <= 1e-13
+    lat.traversal = 0                 # an explicit order replaces both choices
+    out0 = lat.new_spinor()
+    tm.hop_apply(lat, "eo", out0, G64, tm.spinor_import(lat, psi), kappa, THETA_AP)
+    assert torch.equal(out0, out)
