@@ -188,8 +188,11 @@ tmh_status tmh_qtm_apply(tmh_lattice* lat, void* out, const void* gauge, const v
  *           this call, 1/3 fewer link bytes per hop, provided every link's
  *           stored third row matches the conjugate cross product of its
  *           first two to 1e-14 / 1e-7 / 1e-4 (SU(3) links to rounding);
- *           otherwise the 9-entry links are used.  True residuals always
- *           use the caller's 9-entry FP64 links.
+ *           otherwise the 9-entry links are used.  The FP64 residuals
+ *           (the initial one and the true residual after each inner or
+ *           restarted solve) run on an FP64 two-row copy when the links
+ *           pass the FP64 check (1e-14), else on the caller's 9-entry
+ *           links; both are the same operator to rounding.
  *   gauge is always the 9-entry FP64 field.
  * *iters receives the number of operator (Qhat^dagger Qhat) applications in
  * CG recursions (inner ones for mixed precision), *true_rel_res the final

@@ -374,10 +374,11 @@ tmh_status reduce_dot(tmh_lattice* l, double* result, const void* a, const void*
 // r = b - Qhat(-) Qhat(+) x in precision R, and |r|^2 (waits).
 template <typename R>
 tmh_status true_residual(tmh_lattice* l, void* r, const void* b, const void* x, void* v, void* q, void* te,
-                         const void* gauge, double kappa, double mu, const double theta[4], double* rr) {
+                         const void* gauge, double kappa, double mu, const double theta[4], double* rr,
+                         int lf = 0) {
     using W = typename tmh::Word<R>::T;
-    TMH_TRY(qtm_launch<R>(l, v, gauge, x, te, kappa, mu, theta, +1, nullptr, nullptr));
-    TMH_TRY(qtm_launch<R>(l, q, gauge, v, te, kappa, mu, theta, -1, nullptr, nullptr));
+    TMH_TRY(qtm_launch<R>(l, v, gauge, x, te, kappa, mu, theta, +1, nullptr, nullptr, lf));
+    TMH_TRY(qtm_launch<R>(l, q, gauge, v, te, kappa, mu, theta, -1, nullptr, nullptr, lf));
     TMH_TRY_HIP(tmh::launch_sub_norm<R>((W*)r, (const W*)b, (const W*)q, l->partial, l->g, l->stream));
     TMH_TRY_HIP(tmh::launch_reduce(l->scal + tmh::kNorm, l->partial, tmh::blas_blocks(l->g), nullptr,
                                    l->stream));
@@ -390,10 +391,10 @@ tmh_status true_residual(tmh_lattice* l, void* r, const void* b, const void* x, 
 // usual case, which then needs no operator application), else b - A x.
 tmh_status initial_residual(tmh_lattice* l, void* r, const void* b, const void* x, void* v, void* q, void* te,
                             const void* gauge, double kappa, double mu, const double theta[4], double bb,
-                            double* rr) {
+                            double* rr, int lf = 0) {
     double xx;
     TMH_TRY(reduce_dot<double>(l, &xx, x, x));
-    if (xx != 0.0) return true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, rr);
+    if (xx != 0.0) return true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, rr, lf);
     TMH_TRY_HIP(tmh::launch_copy<double>((double2*)r, (const double2*)b, l->g, l->stream));
     *rr = bb;
     return TMH_OK;
@@ -540,7 +541,7 @@ tmh_status cg_fp64(tmh_lattice* l, void* x, const void* b, const void* gauge, do
     int lf;
     TMH_TRY(links64(l, gauge, r12, &gr, &lf));
     double rr;
-    TMH_TRY(initial_residual(l, r, b, x, v, q, te, gauge, kappa, mu, theta, bb, &rr));
+    TMH_TRY(initial_residual(l, r, b, x, v, q, te, gr, kappa, mu, theta, bb, &rr, lf));
     int total = 0;
     for (int restart = 0;; ++restart) {
         *res = sqrt(rr / bb);
@@ -549,7 +550,7 @@ tmh_status cg_fp64(tmh_lattice* l, void* x, const void* b, const void* gauge, do
         int it = 0;
         TMH_TRY(cg_recursion<double>(l, x, r, p, v, q, te, gr, kappa, mu, theta, stop, max_iter - total, &it, lf));
         total += it;
-        TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
+        TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gr, kappa, mu, theta, &rr, lf));
     }
     *iters = total;
     return TMH_ERR_NOT_CONVERGED;
@@ -588,8 +589,13 @@ tmh_status cg_mixed(tmh_lattice* l, void* x, const void* b, const void* gauge, d
         TMH_TRY_HIP(hipStreamSynchronize(l->stream));
         return TMH_OK;
     }
+    // the FP64 residuals run on the FP64 two-row copy when the links pass
+    // its check (the same operator to rounding), else on the caller's links
+    const void* g64;
+    int lf64;
+    TMH_TRY(links64(l, gauge, r12, &g64, &lf64));
     double rr;
-    TMH_TRY(initial_residual(l, r, b, x, v, q, te, gauge, kappa, mu, theta, bb, &rr));
+    TMH_TRY(initial_residual(l, r, b, x, v, q, te, g64, kappa, mu, theta, bb, &rr, lf64));
     int total = 0;
     for (int outer = 0;; ++outer) {
         *res = sqrt(rr / bb);
@@ -606,7 +612,7 @@ tmh_status cg_mixed(tmh_lattice* l, void* x, const void* b, const void* gauge, d
                                 inner * inner * scale * scale * rr, max_iter - total, &it, lf));
         total += it;
         TMH_TRY_HIP(tmh::launch_add_widen<P>((double2*)x, dl, 1.0 / scale, l->g, l->stream));
-        TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, gauge, kappa, mu, theta, &rr));
+        TMH_TRY(true_residual<double>(l, r, b, x, v, q, te, g64, kappa, mu, theta, &rr, lf64));
     }
     *iters = total;
     return TMH_ERR_NOT_CONVERGED;
