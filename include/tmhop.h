@@ -71,6 +71,10 @@
  * Errors.  Every entry point returns a status; nothing aborts or throws.
  * Kernel faults are asynchronous and surface as TMH_ERR_HIP at the next
  * call that waits.
+ *
+ * Threads.  A handle holds scratch, scalars and timing state that every call
+ * on it uses: calls on one handle must not overlap (one handle per host
+ * thread); calls on distinct handles are independent.
  */
 #ifndef TMHOP_H
 #define TMHOP_H
