@@ -79,10 +79,12 @@ def cpu_baseline(dims, U, psi, kappa, theta, budget_s, cg=None):
     oracle.hop(dims, "eo", U, psi, kappa, theta)
     one = time.perf_counter() - t0
     reps = max(1, int(budget_s / max(one, 1e-9)))
-    t0 = time.perf_counter()
+    per = []
     for _ in range(reps):
+        t1 = time.perf_counter()
         oracle.hop(dims, "eo", U, psi, kappa, theta)
-    dt = time.perf_counter() - t0
+        per.append(time.perf_counter() - t1)
+    dt = sum(per)
     cores = oracle.num_threads()
     # the same sample on one thread, bounded to a few applications
     oracle.set_num_threads(1)
@@ -101,6 +103,8 @@ def cpu_baseline(dims, U, psi, kappa, theta, budget_s, cg=None):
         "kind": "oracle",
         "sample": f"{reps} oracle D_eo applications on the {'x'.join(map(str, dims))} fields "
                   f"({Vh} output sites each, {dt:.1f} s)",
+        "median_ms_per_application": round(1e3 * float(np.median(per)), 2),
+        "min_ms_per_application": round(1e3 * min(per), 2),
         "value_1_thread": round(FLOP_PER_SITE * Vh * reps1 / dt1 / 1e9, 3),
         "sample_1_thread": f"{reps1} applications on one thread ({dt1:.1f} s)",
     }
