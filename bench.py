@@ -100,6 +100,7 @@ def cpu_baseline(dims, U, psi, kappa, theta, budget_s, cg=None):
         "value": round(FLOP_PER_SITE * Vh * reps / dt / 1e9, 3),
         "unit": "GFlop/s",
         "cores": cores,
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": f"{reps} oracle D_eo applications on the {'x'.join(map(str, dims))} fields "
                   f"({Vh} output sites each, {dt:.1f} s)",
