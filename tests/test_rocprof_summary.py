@@ -1,0 +1,70 @@
+"""Host logic of the profile summaries (CPU only): the counter calibration
+against the copy kernel and the early-exit accounting of the kernel trace,
+on small synthetic rocprofv3 CSV files."""
+
+import csv
+import json
+
+import pytest
+
+from paper_1311_4521_amd import rocprof_summary as rs
+
+DOM = "void tmh::hop_kernel<double, 0, 0>(tmh::HopArgs<double>)"
+COPY = "tmh::(anonymous namespace)::stream_copy_kernel(unsigned int __vector(4)*)"
+
+
+def write_counters(path, counter, rows):
+    path.mkdir()
+    with open(path / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for k, (name, kib) in enumerate(rows):
+            w.writerow({"Dispatch_Id": k, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": kib})
+
+
+def test_traffic_scales_by_the_copy_kernel(tmp_path):
+    copy_bytes = 805306368
+    # FETCH_SIZE reads half the copy's bytes, WRITE_SIZE all of them
+    write_counters(tmp_path / "f", "FETCH_SIZE",
+                   [(COPY, copy_bytes / 2 / 1024), (DOM, 1000.0), (DOM, 1100.0), ("other", 5.0)])
+    write_counters(tmp_path / "w", "WRITE_SIZE", [(COPY, copy_bytes / 1024), (DOM, 200.0), (DOM, 200.0)])
+    out = tmp_path / "t.json"
+    res = rs.traffic(str(tmp_path / "f"), str(tmp_path / "w"), str(out), copy_bytes=copy_bytes, sites=64)
+    assert res["fetch_scale"] == pytest.approx(2.0) and res["write_scale"] == pytest.approx(1.0)
+    assert res["fetch_bytes_per_launch"] == pytest.approx(2.0 * 1050.0 * 1024)
+    assert res["write_bytes_per_launch"] == pytest.approx(200.0 * 1024)
+    assert res["dispatches"] == [2, 2] and res["sites"] == 64
+    assert res["source_hash"] == rs.hop_source_hash()
+    assert json.load(open(out))["bytes_per_launch"] == pytest.approx(res["bytes_per_launch"])
+
+
+def test_traffic_needs_both_kernels(tmp_path):
+    write_counters(tmp_path / "f", "FETCH_SIZE", [(DOM, 1000.0)])
+    write_counters(tmp_path / "w", "WRITE_SIZE", [(COPY, 1.0), (DOM, 1.0)])
+    with pytest.raises(SystemExit):
+        rs.traffic(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "t.json"))
+
+
+def test_stats_counts_early_exits(tmp_path):
+    d = tmp_path / "prof"
+    d.mkdir()
+    with open(d / "run_kernel_stats.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"])
+        w.writeheader()
+        w.writerow({"Name": DOM, "Calls": 4, "TotalDurationNs": 912000, "AverageNs": 228000, "Percentage": 90.0})
+        w.writerow({"Name": COPY, "Calls": 1, "TotalDurationNs": 100000, "AverageNs": 100000, "Percentage": 10.0})
+    with open(d / "run_kernel_trace.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        t = 0
+        for name, dur in ((DOM, 300000), (DOM, 300000), (DOM, 2000), (DOM, 310000), (COPY, 100000)):
+            w.writerow({"Kernel_Name": name, "Start_Timestamp": t, "End_Timestamp": t + dur})
+            t += dur + 1000
+    out = tmp_path / "s.md"
+    rs.stats(str(d / "run_kernel_stats.csv"), str(out))
+    lines = open(out).read().splitlines()
+    dom = [l for l in lines if "hop_kernel" in l][0].split("|")
+    assert dom[6].strip() == "1"                      # one early exit
+    assert float(dom[7]) == pytest.approx(303.33, abs=0.01)
+    cp = [l for l in lines if "stream_copy" in l][0].split("|")
+    assert cp[6].strip() == "0" and float(cp[7]) == pytest.approx(100.0)
