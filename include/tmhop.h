@@ -247,7 +247,10 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* members, int nmembers, dou
 
 /* Autotuner of the batch tile shape: times the multi-RHS hop of every shape on
  * this lattice for nrhs (<= 16) right-hand sides and keeps the fastest in the
- * handle (used by shape = -1).  With cache_path, a line
+ * handle (used by shape = -1).  It ranks the plain hop; in the batched CG the
+ * last hop of an iteration also updates r and x of every right-hand side,
+ * which favours fewer right-hand sides per thread, so a CG is best tuned by
+ * timing tmh_batch_cg_solve itself for the few fastest shapes.  With cache_path, a line
  * "<arch> <T>x<LX>x<LY>x<LZ> <f64|f32> <nrhs> <shape> <us>" is looked up first
  * and appended after timing.  TMH_F64 and TMH_F32 only.  Blocks. */
 tmh_status tmh_autotune_mrhs(tmh_lattice* lat, const void* gauge, int nrhs, tmh_prec prec,
