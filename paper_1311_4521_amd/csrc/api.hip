@@ -319,6 +319,10 @@ tmh_status qtm_update(tmh_lattice* l, void* x, void* r, const void* p, const voi
     a.c_im[0] = (tmh::real_t<R>)(-kappa * mt / D);
     a.c_re[1] = (tmh::real_t<R>)(kappa / D);
     a.c_im[1] = (tmh::real_t<R>)(kappa * mt / D);
+    // alpha = |r|^2 / (p, A p) from the norm partials of the hop before
+    a.apart = partial;
+    a.napart = tmh::hop_blocks(l->g);
+    a.ascal = l->scal;
     TMH_TRY_HIP(hop_launch<R>(l, a, 0));
     HopArgs<R> b = hop_args<R>(l, 1, nullptr, gauge, te, theta, lf);
     b.done = done;
@@ -423,8 +427,8 @@ tmh_status cg_recursion(tmh_lattice* l, void* x, void* r, void* p, void* v, void
         for (int k = 0; k < kChunk; ++k) {
             // v = Qhat(+) p with |v|^2 = (p, A p)
             TMH_TRY(qtm_launch<R>(l, v, gauge, p, te, kappa, mu, theta, +1, l->partial, l->flags, lf));
-            TMH_TRY_HIP(tmh::launch_cg_alpha<R>(l->scal, l->partial, nb_hop, l->flags, l->stream));
-            // q = Qhat(-) v = A p, fused with r -= alpha q and |r|^2.  The
+            // q = Qhat(-) v = A p, fused with r -= alpha q and |r|^2 (its
+            // first hop also sets alpha from the partials of (p, A p)).  The
             // solution update x += alpha p goes with the last hop in FP64,
             // with the direction update p = r + beta p in FP32 and FP16:
             // measured, each is the faster placement for its precision.

@@ -63,16 +63,6 @@ __global__ void __launch_bounds__(kBlock) cg_init_kernel(double* scal, const dou
     }
 }
 
-__global__ void __launch_bounds__(kBlock) cg_alpha_kernel(double* scal, const double* __restrict__ partial, int n,
-                                                          int* flags) {
-    if (is_done(flags)) return;
-    const double pq = sum_partials(partial, n);
-    if (threadIdx.x == 0) {
-        scal[kPQ] = pq;
-        scal[kAlpha] = scal[kRR] / pq;
-    }
-}
-
 __global__ void __launch_bounds__(kBlock) cg_beta_kernel(double* scal, const double* __restrict__ partial, int n,
                                                          int* flags, int max_iter) {
     if (is_done(flags)) return;
@@ -297,12 +287,6 @@ hipError_t launch_cg_init(double* scal, const double* partial, int n, int* flags
 }
 
 template <typename R>
-hipError_t launch_cg_alpha(double* scal, const double* partial, int n, int* flags, hipStream_t s) {
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(kBlock), 0, s, scal, partial, n, flags);
-    return hipGetLastError();
-}
-
-template <typename R>
 hipError_t launch_cg_xr(typename Word<R>::T* x, typename Word<R>::T* r, const typename Word<R>::T* p,
                         const typename Word<R>::T* q, const double* scal, double* partial, const Geo& g,
                         const int* flags, hipStream_t s) {
@@ -365,7 +349,6 @@ hipError_t launch_zero(typename Word<R>::T* dst, const Geo& g, hipStream_t s) {
 #define TMH_INST(R)                                                                                          \
     template hipError_t launch_dot_partial<R>(double*, const Word<R>::T*, const Word<R>::T*, const Geo&,     \
                                               const int*, hipStream_t);                                      \
-    template hipError_t launch_cg_alpha<R>(double*, const double*, int, int*, hipStream_t);                   \
     template hipError_t launch_cg_xr<R>(Word<R>::T*, Word<R>::T*, const Word<R>::T*, const Word<R>::T*,       \
                                         const double*, double*, const Geo&, const int*, hipStream_t);         \
     template hipError_t launch_cg_p<R>(Word<R>::T*, const Word<R>::T*, const double*, const Geo&, const int*, \

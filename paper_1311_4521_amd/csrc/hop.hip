@@ -78,6 +78,20 @@ template <typename P, int MODE, int LF>
 __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<P> a) {
     using R = real_t<P>;
     if (a.done && *a.done) return;
+    if constexpr (MODE == 0) {
+        // The CG step length from the partials of the preceding twist + norm
+        // hop, summed in a fixed order (thread t takes t, t + 256, ...); it
+        // is read only by the kernels launched after this one.
+        if (a.apart && blockIdx.x == 0) {
+            double s = 0.0;
+            for (int k = threadIdx.x; k < a.napart; k += kHopBlock) s += a.apart[k];
+            s = block_sum<kHopBlock>(s);
+            if (threadIdx.x == 0) {
+                a.ascal[kPQ] = s;
+                a.ascal[kAlpha] = a.ascal[kRR] / s;
+            }
+        }
+    }
     const int i = unit_site(blockIdx.x, threadIdx.x >> 6, gridDim.x, a.xgroup, a.nyb, a.nt, a.g.L[1]) +
                   (threadIdx.x & 63);
     double nrm = 0.0;

@@ -25,6 +25,9 @@ template <typename P> struct HopArgs {
     typename Word<P>::T* xio;         // MODE 4: x += alpha p
     const typename Word<P>::T* pin;   // MODE 4: p
     const double* scal;               // MODE 3: alpha = scal[kAlpha]
+    const double* apart;              // MODE 0, optional: workgroup 0 also sets the CG step,
+    int napart;                       //   ascal[kAlpha] = ascal[kRR] / sum of apart[0..napart)
+    double* ascal;
     const int* done;                  // optional device flag: skip when set
     Geo g;
     int pout;                         // parity of the output sites
@@ -94,8 +97,6 @@ hipError_t launch_reduce(double* out, const double* partial, int n, const int* d
 // CG building blocks on one parity.  scal[] holds the device scalars
 // (see CgScal), flags[] = {done, iterations}.
 enum CgScal { kRR = 0, kPQ = 1, kAlpha = 2, kBeta = 3, kStop = 4, kRRNew = 5, kNorm = 6, kBB = 7, kNScal = 8 };
-template <typename R>
-hipError_t launch_cg_alpha(double* scal, const double* partial, int n, int* flags, hipStream_t s);
 template <typename R>
 hipError_t launch_cg_xr(typename Word<R>::T* x, typename Word<R>::T* r, const typename Word<R>::T* p,
                         const typename Word<R>::T* q, const double* scal, double* partial, const Geo& g,
