@@ -235,9 +235,10 @@ tmh_status tmh_hop_apply_mrhs(tmh_lattice* lat, tmh_dir dir, void* out, const vo
 
 /* CG on Qhat(+)^dagger Qhat(+) for every (member, rhs) system at once (at most
  * 8 members): one launch per operator step for the whole batch, per-system
- * scalars and stopping flags on the device, and, with use_graph != 0, the 8
+ * scalars and stopping flags on the device, and, with use_graph != 0, the 7
  * launches of an iteration captured once into a HIP graph and replayed.
- * Stopping rule, restarts and true residual as tmh_cg_solve, per system.
+ * Stopping rule, restarts and true residual as tmh_cg_solve, per system; a
+ * system whose b is zero gets x = 0 and converges at once, as there.
  * iters[] and true_rel_res[] get one entry per system, members in order.
  * Runs on a private stream ordered after the first member's stream; blocks.
  * TMH_ERR_NOT_CONVERGED if any system missed rel_tol. */

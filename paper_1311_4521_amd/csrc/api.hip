@@ -1263,6 +1263,21 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* m, int nmem, double rel_to
             break;
         }
         if ((st = read_back()) != TMH_OK) break;
+        // A system with b = 0 has the solution x = 0, as in tmh_cg_solve:
+        // its x is cleared here, so that its residual is 0 and the CG
+        // initialisation marks it done before the first iteration.
+        for (int k = 0, mk = 0, r = 0; k < nsys && st == TMH_OK; ++k) {
+            if (h_scal[k * tmh::kNScal + tmh::kBB] == 0.0 && h_scal[k * tmh::kNScal + tmh::kNorm] != 0.0) {
+                const size_t sb = spinor_bytes(m[mk].lat, TMH_F64);
+                if (hipMemsetAsync((char*)m[mk].x + r * sb, 0, sb, s) != hipSuccess) st = TMH_ERR_HIP;
+                h_scal[k * tmh::kNScal + tmh::kNorm] = 0.0;
+            }
+            if (++r == m[mk].nrhs) {
+                ++mk;
+                r = 0;
+            }
+        }
+        if (st != TMH_OK) break;
         bool zero_start = true;
         for (int k = 0; k < nsys; ++k) {
             bb[k] = h_scal[k * tmh::kNScal + tmh::kBB];
@@ -1364,6 +1379,9 @@ tmh_status tmh_autotune_mrhs(tmh_lattice* l, const void* gauge, int nrhs, tmh_pr
              prec == TMH_F64 ? "f64" : "f32", nrhs);
     if (cache_path) {
         if (FILE* f = fopen(cache_path, "r")) {
+            // the outputs are written only on a hit (or after timing)
+            int hit_shape = -1;
+            double hit_us = 0.0;
             char line[512];
             while (fgets(line, sizeof line, f)) {
                 int sh = -1;
@@ -1371,13 +1389,15 @@ tmh_status tmh_autotune_mrhs(tmh_lattice* l, const void* gauge, int nrhs, tmh_pr
                 const size_t kl = strlen(key);
                 if (strncmp(line, key, kl) == 0 && line[kl] == ' ' && sscanf(line + kl, " %d %lf", &sh, &us) == 2 &&
                     sh >= 0 && sh < tmh::kNumShapes) {
-                    *best_shape = sh;
-                    *best_us = us;
+                    hit_shape = sh;
+                    hit_us = us;
                 }
             }
             fclose(f);
-            if (*best_shape >= 0 && *best_shape < tmh::kNumShapes && *best_us > 0.0) {
-                l->tuned[prec][nrhs] = *best_shape;
+            if (hit_shape >= 0 && hit_us > 0.0) {
+                *best_shape = hit_shape;
+                *best_us = hit_us;
+                l->tuned[prec][nrhs] = hit_shape;
                 return TMH_OK;
             }
         }

@@ -144,3 +144,41 @@ def test_autotune_and_cache(tmp_path):
     sh2, us2 = tm.autotune_mrhs(lat2, tm.gauge_import(lat2, haar(dims, 551)), 12, tm.F64, cache)
     assert (sh2, us2) == (sh, float(text[5]))
     assert len(open(cache).read().strip().splitlines()) == 1
+
+
+@pytest.mark.parametrize("use_graph", [False, True], ids=["eager", "graph"])
+def test_batch_zero_source_nonzero_start(use_graph):
+    """A system with b = 0 and a start vector that is not zero gets x = 0 and
+    residual 0 without holding back the others (as tmh_cg_solve does), alone
+    in a batch and beside other systems."""
+    kappa, mu = 0.1632, mu_of(0.1632, 0.0013)
+    dims = (4, 4, 4, 4)
+    lat = tm.Lattice(dims)
+    U = haar(dims, 25)
+    G = tm.gauge_import(lat, U)
+    # alone: one member, one system
+    x = lat.new_spinors(1)
+    x.fill_(1.0)
+    b = lat.new_spinors(1)
+    it, res, ok = tm.batch_cg_solve([dict(lat=lat, x=x, b=b, gauge=G, kappa=kappa, mu=mu, theta=THETA_AP)],
+                                    1e-10, 100, -1, use_graph)
+    assert ok and it == [0] and res == [0.0] and float(x.abs().max()) == 0.0
+    # beside two systems with Gaussian sources, on a second lattice as well
+    dims2 = (6, 8, 10, 4)
+    lat2 = tm.Lattice(dims2)
+    U2 = haar(dims2, 531)
+    bs = [gauss(lat.Vh, 26), np.zeros((lat.Vh, 4, 3), np.complex128), gauss(lat.Vh, 27)]
+    b3 = import_many(lat, bs)
+    x3 = lat.new_spinors(3)
+    x3[1].fill_(0.25)
+    b2 = import_many(lat2, [gauss(lat2.Vh, 28)])
+    x2 = lat2.new_spinors(1)
+    members = [dict(lat=lat, x=x3, b=b3, gauge=G, kappa=kappa, mu=mu, theta=THETA_AP),
+               dict(lat=lat2, x=x2, b=b2, gauge=tm.gauge_import(lat2, U2), kappa=kappa, mu=mu, theta=THETA_AP)]
+    it, res, ok = tm.batch_cg_solve(members, 1e-10, 500, -1, use_graph)
+    assert ok and it[1] == 0 and res[1] == 0.0 and float(x3[1].abs().max()) == 0.0
+    assert max(it) < 500
+    for r in (0, 2):
+        xs = host(tm.spinor_export(lat, x3[r]))
+        rr = bs[r] - oracle.normal(dims, U, xs, kappa, mu, THETA_AP)
+        assert np.linalg.norm(rr) / np.linalg.norm(bs[r]) <= 1.05e-10, r

@@ -92,9 +92,10 @@ def set_link(G, dims, mu, lex, M):
     G[p, mu, :, lex >> 1, :] = t
 
 
-@pytest.mark.slow
-def test_force_24x24x24x48_oracle_and_finite_differences():
-    """The adjoint workload: 24^3x48 Haar links, Gaussian chi and psi."""
+@pytest.fixture(scope="module")
+def adjoint24():
+    """The adjoint workload: 24^3x48 Haar links, Gaussian chi and psi, on the
+    GPU and on the host."""
     dims, kappa, mt = (48, 24, 24, 24), 0.1632, 0.0013
     mu = mu_of(kappa, mt)
     seed = fieldgen.SEEDS["adjoint24"]
@@ -103,30 +104,71 @@ def test_force_24x24x24x48_oracle_and_finite_differences():
     chi, psi = gauss(Vh, 100 + seed), gauss(Vh, 200 + seed)
     lat = tm.Lattice(dims)
     G = tm.gauge_import(lat, U)
-    tc, tp = tm.spinor_import(lat, chi), tm.spinor_import(lat, psi)
-    F = lat.new_gauge(zero=True)
-    tm.qtm_force(lat, F, G, tc, tp, kappa, mu, THETA_AP, +1)
-    Fh = host(tm.gauge_export(lat, F))
-    ref = oracle.qtm_force(dims, U, chi, psi, kappa, mu, THETA_AP, +1)
-    assert link_rel_err(Fh, ref) <= 1e-13
-    # central differences on the GPU at sampled links (boundary and interior)
+    return dict(dims=dims, kappa=kappa, mu=mu, U=U, chi=chi, psi=psi, lat=lat, G=G,
+                tc=tm.spinor_import(lat, chi), tp=tm.spinor_import(lat, psi))
+
+
+def fd_links(dims):
+    """Sampled links for the finite differences: both ends of the lattice,
+    one past the middle, and nine drawn from a seeded generator."""
     g = fieldgen.rng(331)
     V = int(np.prod(dims))
-    links = [(0, 0), (0, V - 1), (3, V // 2 + 7)] + \
+    return [(0, 0), (0, V - 1), (3, V // 2 + 7)] + \
         [(int(g.integers(0, 4)), int(g.integers(0, V))) for _ in range(9)]
+
+
+def central_differences(w, links, h, Fh, local_diff):
+    """Per link: the 8 su(3) components of central differences of step h
+    (local_diff(q_plus, q_minus) returns L(+h) - L(-h), formed from site-wise
+    differences) against tr(T^a F) of the analytic force."""
+    lat, G, U, tp = w["lat"], w["G"], w["U"], w["tp"]
     qp, qm = lat.new_spinor(), lat.new_spinor()
-    h = 1e-6
     for mu_, l in links:
         fd = np.empty(8)
         for a in range(8):
             Gp = G.clone()
-            set_link(Gp, dims, mu_, l, expm_herm(h * fieldgen.gell_mann()[a] / 2) @ U[mu_, l])
-            tm.qtm_apply(lat, qp, Gp, tp, kappa, mu, THETA_AP, +1)
-            set_link(Gp, dims, mu_, l, expm_herm(-h * fieldgen.gell_mann()[a] / 2) @ U[mu_, l])
-            tm.qtm_apply(lat, qm, Gp, tp, kappa, mu, THETA_AP, +1)
-            fd[a] = tm.scalar_prod_r(lat, tc, qp - qm) / (2 * h)
+            set_link(Gp, w["dims"], mu_, l, expm_herm(h * fieldgen.gell_mann()[a] / 2) @ U[mu_, l])
+            tm.qtm_apply(lat, qp, Gp, tp, w["kappa"], w["mu"], THETA_AP, +1)
+            set_link(Gp, w["dims"], mu_, l, expm_herm(-h * fieldgen.gell_mann()[a] / 2) @ U[mu_, l])
+            tm.qtm_apply(lat, qm, Gp, tp, w["kappa"], w["mu"], THETA_AP, +1)
+            fd[a] = local_diff(qp, qm) / (2 * h)
         an = np.array([np.trace(GEN[a] @ Fh[mu_, l]).real for a in range(8)])
         assert np.linalg.norm(fd - an) / np.linalg.norm(an) < 1e-6, (mu_, l)
+
+
+@pytest.mark.slow
+def test_force_24x24x24x48_oracle_and_finite_differences(adjoint24):
+    """L = Re<chi, Qhat psi>: the force against the oracle per link, and
+    central differences L(+h) - L(-h) = Re<chi, Qhat(+h) psi - Qhat(-h) psi>."""
+    w = adjoint24
+    lat = w["lat"]
+    F = lat.new_gauge(zero=True)
+    tm.qtm_force(lat, F, w["G"], w["tc"], w["tp"], w["kappa"], w["mu"], THETA_AP, +1)
+    Fh = host(tm.gauge_export(lat, F))
+    ref = oracle.qtm_force(w["dims"], w["U"], w["chi"], w["psi"], w["kappa"], w["mu"], THETA_AP, +1)
+    assert link_rel_err(Fh, ref) <= 1e-13
+    central_differences(w, fd_links(w["dims"]), 1e-6, Fh,
+                        lambda qp, qm: tm.scalar_prod_r(lat, w["tc"], qp - qm))
+
+
+@pytest.mark.slow
+def test_force_24x24x24x48_norm2_oracle_and_finite_differences(adjoint24):
+    """L = |Qhat psi|^2: the force is that of Re<chi, Qhat psi> at
+    chi = 2 Qhat psi (GPU against the oracle fed the oracle's own 2 Qhat psi);
+    central differences L(+h) - L(-h) = |a|^2 - |b|^2 formed as Re<a - b, a + b>
+    with a, b = Qhat(+-h) psi, so that sites the link cannot reach cancel."""
+    w = adjoint24
+    lat, dims, U = w["lat"], w["dims"], w["U"]
+    q = lat.new_spinor()
+    tm.qtm_apply(lat, q, w["G"], w["tp"], w["kappa"], w["mu"], THETA_AP, +1)
+    F = lat.new_gauge(zero=True)
+    tm.qtm_force(lat, F, w["G"], 2.0 * q, w["tp"], w["kappa"], w["mu"], THETA_AP, +1)
+    Fh = host(tm.gauge_export(lat, F))
+    chi2 = 2.0 * oracle.qtm(dims, U, w["psi"], w["kappa"], w["mu"], THETA_AP, +1)
+    ref = oracle.qtm_force(dims, U, chi2, w["psi"], w["kappa"], w["mu"], THETA_AP, +1)
+    assert link_rel_err(Fh, ref) <= 1e-13
+    central_differences(w, fd_links(dims), 1e-6, Fh,
+                        lambda qp, qm: tm.scalar_prod_r(lat, qp - qm, qp + qm))
 
 
 def test_autograd_gradcheck_bilinear():
