@@ -93,7 +93,9 @@ typedef enum {
     TMH_ERR_HIP = -4,           /* a HIP runtime call failed                  */
     TMH_ERR_NOMEM = -5,         /* device allocation of scratch failed        */
     TMH_ERR_NOT_CONVERGED = -6, /* CG hit max_iter; x holds the last iterate  */
-    TMH_ERR_UNSUPPORTED = -7    /* precision or feature not built             */
+    TMH_ERR_UNSUPPORTED = -7,   /* precision or feature not built             */
+    TMH_ERR_SCRATCH = -8        /* field exceeds the fixed scratch of an
+                                   allocation-free call                        */
 } tmh_status;
 
 typedef enum { TMH_EO = 0 /* odd -> even */, TMH_OE = 1 /* even -> odd */ } tmh_dir;
@@ -168,6 +170,25 @@ tmh_status tmh_hop_apply(tmh_lattice* lat, tmh_dir dir, void* out, const void* g
 tmh_status tmh_qtm_apply(tmh_lattice* lat, void* out, const void* gauge, const void* in,
                          double kappa, double mu, const double theta[4], int sign,
                          tmh_prec prec);
+
+/* Allocation-free tmh_qtm_apply, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same operation, arguments, checks and result (bitwise)
+ * as tmh_qtm_apply, enqueued on the handle's stream, with no hipMalloc,
+ * hipFree, event or other allocation inside the call, and no launch timing
+ * (tmh_profile_* does not see it).  The intermediate even field lives in a
+ * fixed device array of TMH_NOALLOC_MAX_BYTES bytes that the library holds
+ * on every GPU it runs on until the process ends (its address is looked up
+ * at tmh_lattice_create).  All calls on one GPU share that array: calls that
+ * may overlap on one GPU (other streams, other host threads) race and must
+ * not be issued.  The array needs no clearing: each call writes the field in
+ * full before reading it.  TMH_ERR_SCRATCH if tmh_spinor_bytes(lat, prec)
+ * exceeds TMH_NOALLOC_MAX_BYTES (64 MiB: FP64 up to 349,525 sites per
+ * parity, e.g. 24^3x48). */
+#define TMH_NOALLOC_MAX_BYTES (64u << 20)
+tmh_status tmh_qtm_apply_noalloc(tmh_lattice* lat, void* out, const void* gauge, const void* in,
+                                 double kappa, double mu, const double theta[4], int sign,
+                                 tmh_prec prec);
 
 /* CG (the paper's inverter, Section 3) on Qhat(+)^dagger Qhat(+) x = b.
  * x (FP64 internal layout, odd) holds the initial guess on entry and the

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/tmhop.h"
+#include "api_internal.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -250,7 +251,8 @@ hipError_t hop_launch(tmh_lattice* l, const HopArgs<R>& a, int mode) {
 // second launch also writes the |out|^2 partials.
 template <typename R>
 tmh_status qtm_launch(tmh_lattice* l, void* out, const void* gauge, const void* in, void* te, double kappa,
-                      double mu, const double theta[4], int sign, double* partial, const int* done, int lf = 0) {
+                      double mu, const double theta[4], int sign, double* partial, const int* done, int lf = 0,
+                      bool timed = true) {
     const double mt = 2.0 * kappa * mu * sign;
     const double D = 1.0 + mt * mt;
     HopArgs<R> a = hop_args<R>(l, 0, te, gauge, in, theta, lf);
@@ -260,7 +262,7 @@ tmh_status qtm_launch(tmh_lattice* l, void* out, const void* gauge, const void* 
     a.c_im[0] = (tmh::real_t<R>)(-kappa * mt / D);
     a.c_re[1] = (tmh::real_t<R>)(kappa / D);
     a.c_im[1] = (tmh::real_t<R>)(kappa * mt / D);
-    TMH_TRY_HIP(hop_launch<R>(l, a, 0));
+    TMH_TRY_HIP(timed ? hop_launch<R>(l, a, 0) : tmh::launch_hop<R>(a, 0, l->stream));
     HopArgs<R> b = hop_args<R>(l, 1, out, gauge, te, theta, lf);
     b.done = done;
     b.aux = (const typename tmh::Word<R>::T*)in;
@@ -273,7 +275,8 @@ tmh_status qtm_launch(tmh_lattice* l, void* out, const void* gauge, const void* 
     b.d_im[0] = (tmh::real_t<R>)mt;
     b.d_re[1] = (tmh::real_t<R>)-1;
     b.d_im[1] = (tmh::real_t<R>)mt;
-    TMH_TRY_HIP(hop_launch<R>(l, b, partial ? 2 : 1));
+    const int mode = partial ? 2 : 1;
+    TMH_TRY_HIP(timed ? hop_launch<R>(l, b, mode) : tmh::launch_hop<R>(b, mode, l->stream));
     return TMH_OK;
 }
 
@@ -635,6 +638,35 @@ tmh_status cg_dispatch(tmh_lattice* l, void* x, const void* b, const void* gauge
 
 }  // namespace
 
+namespace tmh_api {
+
+tmh_status qtm_check(const tmh_lattice* l, const void* out, const void* gauge, const void* in, double kappa,
+                     double mu, const double theta[4], int sign, tmh_prec prec) {
+    TMH_TRY(check_lat(l));
+    TMH_TRY(check_prec(prec));
+    TMH_TRY(check_theta(theta));
+    if (sign != 1 && sign != -1) return TMH_ERR_ARG;
+    if (!out || !gauge || !in || !isfinite(kappa) || !isfinite(mu)) return TMH_ERR_ARG;
+    const size_t sb = spinor_bytes(l, prec);
+    if (overlap(out, sb, in, sb) || overlap(out, sb, gauge, gauge_bytes(l, prec))) return TMH_ERR_ALIAS;
+    return TMH_OK;
+}
+
+tmh_status qtm_run(tmh_lattice* l, void* out, const void* gauge, const void* in, void* te, double kappa,
+                   double mu, const double theta[4], int sign, tmh_prec prec, bool timed) {
+    const int lf = link_format(prec);
+    return dispatch(prec, [&](auto tag) {
+        using P = decltype(tag);
+        return qtm_launch<P>(l, out, gauge, in, te, kappa, mu, theta, sign, nullptr, nullptr, lf, timed);
+    });
+}
+
+int lattice_device(const tmh_lattice* l) { return l->device; }
+
+size_t lattice_spinor_bytes(const tmh_lattice* l, tmh_prec prec) { return spinor_bytes(l, prec); }
+
+}  // namespace tmh_api
+
 extern "C" {
 
 tmh_status tmh_lattice_create(tmh_lattice** out, const int dims[4], int device, void* hip_stream) {
@@ -664,6 +696,9 @@ tmh_status tmh_lattice_create(tmh_lattice** out, const int dims[4], int device, 
     for (auto& row : l->tuned)
         for (int& v : row) v = -1;
     l->xgroup = default_xgroup(l);
+    // address of this device's fixed scratch (allocation-free entry points);
+    // a failure here is reported by those entry points, which query again
+    (void)tmh_api::noalloc_setup(device);
     const int nh = tmh::hop_blocks(l->g), nbl = tmh::blas_blocks(l->g);
     l->npartial = nh > nbl ? nh : nbl;
     tmh_status st = ensure((void**)&l->partial, sizeof(double) * l->npartial);
@@ -796,21 +831,11 @@ tmh_status tmh_hop_apply(tmh_lattice* l, tmh_dir dir, void* out, const void* gau
 
 tmh_status tmh_qtm_apply(tmh_lattice* l, void* out, const void* gauge, const void* in, double kappa, double mu,
                          const double theta[4], int sign, tmh_prec prec) {
-    TMH_TRY(check_lat(l));
-    TMH_TRY(check_prec(prec));
-    TMH_TRY(check_theta(theta));
-    if (sign != 1 && sign != -1) return TMH_ERR_ARG;
-    if (!out || !gauge || !in || !isfinite(kappa) || !isfinite(mu)) return TMH_ERR_ARG;
-    const size_t sb = spinor_bytes(l, prec);
-    if (overlap(out, sb, in, sb) || overlap(out, sb, gauge, gauge_bytes(l, prec))) return TMH_ERR_ALIAS;
+    TMH_TRY(tmh_api::qtm_check(l, out, gauge, in, kappa, mu, theta, sign, prec));
     DeviceGuard guard(l->device);
     void* te;
     TMH_TRY(even_scratch(l, prec, &te));
-    const int lf = link_format(prec);
-    return dispatch(prec, [&](auto tag) {
-        using P = decltype(tag);
-        return qtm_launch<P>(l, out, gauge, in, te, kappa, mu, theta, sign, nullptr, nullptr, lf);
-    });
+    return tmh_api::qtm_run(l, out, gauge, in, te, kappa, mu, theta, sign, prec, true);
 }
 
 tmh_status tmh_cg_solve(tmh_lattice* l, void* x, const void* b, const void* gauge, double kappa, double mu,
@@ -1636,6 +1661,7 @@ const char* tmh_status_string(tmh_status st) {
         case TMH_ERR_NOMEM: return "device allocation failed";
         case TMH_ERR_NOT_CONVERGED: return "CG did not converge within max_iter";
         case TMH_ERR_UNSUPPORTED: return "unsupported precision or feature";
+        case TMH_ERR_SCRATCH: return "field larger than the fixed scratch of the allocation-free call";
     }
     return "unknown status";
 }

@@ -39,9 +39,12 @@ TMH_ERR_HIP = -4
 TMH_ERR_NOMEM = -5
 TMH_ERR_NOT_CONVERGED = -6
 TMH_ERR_UNSUPPORTED = -7
+TMH_ERR_SCRATCH = -8
+NOALLOC_MAX_BYTES = 64 << 20  # TMH_NOALLOC_MAX_BYTES
 
 EO, OE = 0, 1
 XSLAB = -8  # traversal: one x-slab per XCD (TMH_TRAVERSAL_XSLAB)
+
 # precision codes: spinor word and link storage (F64_R12 / F32_R12 keep each
 # link as its first two rows, the third rebuilt in the kernels; SU(3) only)
 # F16 / F16_R12: FP16 storage with FP32 arithmetic
@@ -78,6 +81,7 @@ _sig("tmh_spinor_import", _I, [_P, _P, _P, _I])
 _sig("tmh_spinor_export", _I, [_P, _P, _P, _I])
 _sig("tmh_hop_apply", _I, [_P, _I, _P, _P, _P, _D, _P, _I])
 _sig("tmh_qtm_apply", _I, [_P, _P, _P, _P, _D, _D, _P, _I, _I])
+_sig("tmh_qtm_apply_noalloc", _I, [_P, _P, _P, _P, _D, _D, _P, _I, _I])
 _sig("tmh_cg_solve", _I, [_P, _P, _P, _P, _D, _D, _P, _D, _I, _I, ctypes.POINTER(_I),
                           ctypes.POINTER(_D)])
 _sig("tmh_hop_force", _I, [_P, _I, _P, _P, _P, _P, _D, _P, _D, _I])
@@ -109,7 +113,7 @@ EXPORTED = ("tmh_lattice_create", "tmh_lattice_destroy", "tmh_lattice_set_stream
             "tmh_lattice_set_traversal", "tmh_lattice_traversal", "tmh_autotune_hop",
             "tmh_half_volume", "tmh_site_stride", "tmh_spinor_bytes", "tmh_gauge_bytes",
             "tmh_gauge_import", "tmh_spinor_import", "tmh_spinor_export", "tmh_hop_apply",
-            "tmh_qtm_apply", "tmh_cg_solve", "tmh_hop_force", "tmh_qtm_force", "tmh_gauge_export", "tmh_solve_full", "tmh_hop_apply_mrhs",
+            "tmh_qtm_apply", "tmh_qtm_apply_noalloc", "tmh_cg_solve", "tmh_hop_force", "tmh_qtm_force", "tmh_gauge_export", "tmh_solve_full", "tmh_hop_apply_mrhs",
             "tmh_batch_cg_solve", "tmh_autotune_mrhs",
             "tmh_scalar_prod_r", "tmh_norm2",
             "tmh_stream_copy", "tmh_profile_enable", "tmh_profile_read", "tmh_status_string")
@@ -298,6 +302,22 @@ def qtm_apply(lat: Lattice, out, gauge, inp, kappa, mu, theta, sign=+1, prec=F64
     lat._sync_stream()
     _check(_lib.tmh_qtm_apply(lat.handle, out.data_ptr(), gauge.data_ptr(), inp.data_ptr(),
                               float(kappa), float(mu), th, int(sign), p), "tmh_qtm_apply")
+    return out
+
+
+def qtm_apply_noalloc(lat: Lattice, out, gauge, inp, kappa, mu, theta, sign=+1, prec=F64):
+    """out = Qhat(sign) inp like qtm_apply, with the intermediate field in the
+    library's fixed device scratch (no device allocation in the call);
+    asynchronous.  Raises TmhError(TMH_ERR_SCRATCH) for fields larger than
+    NOALLOC_MAX_BYTES."""
+    p = _PRECS[prec]
+    _expect(out, lat, p, "spinor")
+    _expect(inp, lat, p, "spinor")
+    _expect(gauge, lat, p, "gauge")
+    th, _keep = _theta(theta)
+    lat._sync_stream()
+    _check(_lib.tmh_qtm_apply_noalloc(lat.handle, out.data_ptr(), gauge.data_ptr(), inp.data_ptr(),
+                                      float(kappa), float(mu), th, int(sign), p), "tmh_qtm_apply_noalloc")
     return out
 
 

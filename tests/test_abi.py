@@ -47,7 +47,7 @@ def test_bad_geometry_rejected(dims):
 
 def test_status_strings():
     from paper_1311_4521_amd import tmhop
-    for st in range(-7, 1):
+    for st in range(-8, 1):
         assert tmhop.status_string(st) not in ("", "unknown status")
     assert tmhop.status_string(-99) == "unknown status"
 
