@@ -133,10 +133,22 @@ tmh_status tmh_lattice_set_stream(tmh_lattice* lat, void* hip_stream);
  * default is the largest xgroup with xgroup * LY * LZ / 2 <= 8192 when the
  * geometry tiles (LY*LZ/2 a multiple of 64, T a multiple of 8, xgroup
  * divides LX, V/2 a multiple of 2048); tmh_autotune_hop measures every
- * order instead.  TMH_ERR_UNSUPPORTED if the geometry does not tile for this
- * order, TMH_ERR_ARG for other negative values.  tmh_lattice_traversal
+ * order instead (and the t-marching kernel below for the step counts whose
+ * grids hold 64 to 4096 workgroups).  TMH_ERR_UNSUPPORTED if the geometry
+ * does not tile for this order, TMH_ERR_ARG for other negative values.  tmh_lattice_traversal
  * returns the current value (-1 for a null handle). */
 #define TMH_TRAVERSAL_XSLAB (-8)
+/* t-marching hop kernel: the two sites (x, y, 2zp) and (x, y, 2zp+1) of one
+ * time-slice are a pair whose sites alternate between the two parities with
+ * t, so that the time neighbours of the output site of a pair at t are the
+ * input sites of the same pair at t-1 and t+1.  Each thread owns a pair,
+ * each workgroup a tile of 256 pairs, and walks `steps` consecutive
+ * time-slices, keeping the input spinors of its pair at t-1, t and t+1 in
+ * registers: the time neighbours are read from memory once, the spatial
+ * ones from the caches while the neighbouring tiles of the same XCD work on
+ * the same slice.  Valid when steps divides T and LX*LY*LZ/2 is a multiple
+ * of 256. */
+#define TMH_TRAVERSAL_TMARCH(steps) (-1024 - (steps))
 tmh_status tmh_lattice_set_traversal(tmh_lattice* lat, int xgroup);
 int tmh_lattice_traversal(const tmh_lattice* lat);
 
@@ -278,9 +290,11 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* members, int nmembers, dou
 tmh_status tmh_autotune_mrhs(tmh_lattice* lat, const void* gauge, int nrhs, tmh_prec prec,
                              const char* cache_path, int* best_shape, double* best_us);
 
-/* Autotuner of the hop traversal: times tmh_hop_apply in precision prec for
- * xgroup = 0, TMH_TRAVERSAL_XSLAB and every valid group on this lattice and
- * returns the fastest.  The handle keeps it for every later launch of that
+/* Autotuner of the hop traversal: times chains of tmh_hop_apply (each hop
+ * reading the previous one's output, as in the solvers) in precision prec
+ * for xgroup = 0, TMH_TRAVERSAL_XSLAB, every valid group and the valid
+ * TMH_TRAVERSAL_TMARCH step counts whose grids hold 64 to 4096 workgroups on
+ * this lattice and returns the fastest.  The handle keeps it for every later launch of that
  * storage code (hop, qtm and the CG recursions, including the inner solves
  * of tmh_cg_solve) and as its order for the codes not tuned;
  * tmh_lattice_set_traversal discards the per-code choices.  With cache_path, a line "<arch> <T>x<LX>x<LY>x<LZ> <prec> hop

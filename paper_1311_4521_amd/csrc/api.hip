@@ -136,7 +136,17 @@ tmh_status ensure(void** p, size_t bytes) {
 // The x-slab traversal needs whole planes, LX a multiple of 8 and a whole
 // number of workgroups per XCD.
 static_assert(tmh::kXSlab == TMH_TRAVERSAL_XSLAB, "the kernels and the ABI name the x-slab order alike");
+static_assert(tmh::kTMarch0 - 4 == TMH_TRAVERSAL_TMARCH(4), "the kernels and the ABI name the t-march alike");
+// Steps per workgroup of a t-march traversal code, 0 for other codes.
+int tmarch_steps(int code) { return code < tmh::kTMarch0 ? tmh::kTMarch0 - code : 0; }
+// The t-march needs whole tiles of kHopThreads pairs per time-slice and a
+// whole number of ranges of `steps` time-slices.
+bool tmarch_ok(const tmh_lattice* l, int steps) {
+    const int64_t slice = (int64_t)l->dims[1] * l->dims[2] * l->dims[3] / 2;
+    return steps >= 1 && steps <= l->dims[0] && l->dims[0] % steps == 0 && slice % tmh::kHopThreads == 0;
+}
 bool xgroup_ok(const tmh_lattice* l, int xg) {
+    if (tmarch_steps(xg) > 0) return tmarch_ok(l, tmarch_steps(xg));
     const int plane = l->dims[2] * l->dims[3] / 2;
     const bool tiles = plane % 64 == 0 && l->g.Vh % (64 * 8) == 0 &&
                        (l->g.Vh / 64 / 8) % (tmh::kHopThreads / 64) == 0;
@@ -190,7 +200,13 @@ HopArgs<R> hop_args(const tmh_lattice* l, int pout, void* out, const void* gauge
     a.lf = lf;
     const int code = prec_code<R>(lf);
     const int xg = l->xtuned[code] ? l->xgroup_code[code] : l->xgroup;
-    if (xgroup_ok(l, xg)) {
+    if (tmarch_steps(xg) > 0) {
+        if (tmarch_ok(l, tmarch_steps(xg))) {
+            a.tm_steps = tmarch_steps(xg);
+            a.tm_slice = l->dims[1] * l->dims[2] * l->dims[3] / 2;
+            a.tm_nw = a.tm_slice / tmh::kHopThreads;
+        }
+    } else if (xgroup_ok(l, xg)) {
         a.xgroup = xg;
         a.nyb = l->dims[2] * l->dims[3] / 2 / 64;
         a.nt = l->dims[0] / 8;
@@ -746,7 +762,7 @@ void tmh_lattice_destroy(tmh_lattice* l) {
 
 tmh_status tmh_lattice_set_traversal(tmh_lattice* l, int xgroup) {
     TMH_TRY(check_lat(l));
-    if (xgroup < 0 && xgroup != TMH_TRAVERSAL_XSLAB) return TMH_ERR_ARG;
+    if (xgroup < 0 && xgroup != TMH_TRAVERSAL_XSLAB && tmarch_steps(xgroup) == 0) return TMH_ERR_ARG;
     if (xgroup != 0 && !xgroup_ok(l, xgroup)) return TMH_ERR_UNSUPPORTED;
     l->xgroup = xgroup;
     for (bool& t : l->xtuned) t = false;  // an explicit order applies to every code
@@ -1540,6 +1556,12 @@ tmh_status tmh_autotune_hop(tmh_lattice* l, const void* gauge, tmh_prec prec, co
     if (xgroup_ok(l, tmh::kXSlab)) cands.push_back(tmh::kXSlab);
     for (int xg = 1; xg <= l->dims[1]; ++xg)
         if (xgroup_ok(l, xg)) cands.push_back(xg);
+    // t-march step counts whose grids hold between 64 and 4096 workgroups
+    for (int st = 1; st <= l->dims[0]; ++st)
+        if (tmarch_ok(l, st)) {
+            const int nb = tmh::hop_tmarch_blocks(l->g, st);
+            if (nb >= 64 && nb <= 4096) cands.push_back(tmh::kTMarch0 - st);
+        }
     // two rounds over the candidates, each candidate's time the smaller of
     // its two, so that a drift of the clock or of other load during one
     // round does not decide between orders a few per cent apart
@@ -1549,12 +1571,17 @@ tmh_status tmh_autotune_hop(tmh_lattice* l, const void* gauge, tmh_prec prec, co
             const int xg = cands[ci];
             l->xgroup = xg;
             l->xgroup_code[prec] = xg;
+            // a chain of hops, each reading what the previous one wrote, as
+            // inside the solvers (a hop repeated on one input finds more of
+            // it in the caches)
             for (int w = 0; w < 2 && st == TMH_OK; ++w)
-                st = tmh_hop_apply(l, TMH_EO, out, gauge, in, 0.1, theta, prec);
+                st = tmh_hop_apply(l, w % 2 ? TMH_OE : TMH_EO, w % 2 ? in : out, gauge, w % 2 ? out : in, 0.1,
+                                   theta, prec);
             const int reps = 6;
             if (st == TMH_OK && hipEventRecord(e0, l->stream) != hipSuccess) st = TMH_ERR_HIP;
             for (int k = 0; k < reps && st == TMH_OK; ++k)
-                st = tmh_hop_apply(l, k % 2 ? TMH_OE : TMH_EO, out, gauge, in, 0.1, theta, prec);
+                st = tmh_hop_apply(l, k % 2 ? TMH_OE : TMH_EO, k % 2 ? in : out, gauge, k % 2 ? out : in, 0.1,
+                                   theta, prec);
             float ms = 0.f;
             if (st == TMH_OK && (hipEventRecord(e1, l->stream) != hipSuccess ||
                                  hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))

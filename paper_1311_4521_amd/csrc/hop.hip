@@ -141,6 +141,196 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<P> 
 
 int hop_blocks(const Geo& g) { return (g.Vh + kHopBlock - 1) / kHopBlock; }
 
+// ------------------------------------------------------------ t-marching
+//
+// A site x = (t, x, y, z) and its neighbour x + z^ or x - z^ with z even/odd
+// share the even-odd index of their time-slice: the two sites (x, y, 2zp)
+// and (x, y, 2zp + 1) form a pair, and at every t one of them is on the
+// output parity and the other on the input parity.  The two time neighbours
+// of the output site of pair j at t are the input sites of the same pair at
+// t - 1 and t + 1.  A thread owns one pair of a tile of kHopBlock pairs and
+// walks tm_steps consecutive time-slices; it loads the input site of its pair
+// at t + 1 (the forward time neighbour) once, and keeps it in registers for
+// the next two steps, where it is the pair's own input site and then the
+// backward time neighbour.  Neither time neighbour is read from memory twice;
+// the six spatial neighbours of the slice in progress are read from the
+// caches, where the tiles of the same XCD working on the same slice have
+// just brought them.  XCD k runs one contiguous range of (t-range, tile)
+// workgroups, i.e. a contiguous part of one range of time-slices.
+
+template <typename P>
+__device__ __forceinline__ void load_psi(cx<real_t<P>> (&psi)[4][3], const typename Word<P>::T* __restrict__ in,
+                                         int S, int j) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) psi[s][c] = bload<P>(in + (int64_t)(3 * s + c) * S, S, j);
+}
+
+// The link of term T only (its spinor comes from the registers).
+template <typename P, int T, int LAUX, int LF>
+__device__ __forceinline__ void load_link_t(TermData<real_t<P>>& d, const HopArgs<P>& a, const SiteNb& n, int i) {
+    constexpr int MU = T / 2;
+    constexpr int NC = link_comps<LF>();
+    const int S = a.g.S;
+    const typename Word<P>::T* link = (T % 2 == 0 ? a.gout : a.gin) + (int64_t)MU * NC * S;
+    const int jl = T % 2 == 0 ? i : n.jn[T];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) d.u[k / 3][k % 3] = bload<P, LAUX>(link + (int64_t)k * S, S, jl);
+    if constexpr (LF == 1) third_row<real_t<P>>(d.u);
+}
+
+// The 8 terms of one output site in the t-march: term 0 (forward t) loads
+// psi(t + 1) from memory, term 1 (backward t) takes psi(t - 1) = prev from the
+// registers; afterwards the ring advances (prev <- cur <- psi(t + 1)).
+template <typename P, int LAUX, int LF>
+__device__ __forceinline__ void hop_site_tm(cx<real_t<P>> (&acc)[4][3], const HopArgs<P>& a, const SiteNb& n, int i,
+                                            cx<real_t<P>> (&prev)[4][3], cx<real_t<P>> (&cur)[4][3]) {
+    using R = real_t<P>;
+    TermData<R> d0, d1;
+    load_t<P, 0, LAUX, LF>(d0, a, n, i);
+    TMH_SCHED_FENCE();
+    load_link_t<P, 1, LAUX, LF>(d1, a, n, i);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d1.psi[s][c] = prev[s][c];
+    TMH_SCHED_FENCE();
+    add_t<P, 0>(acc, d0, a, n);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            prev[s][c] = cur[s][c];
+            cur[s][c] = d0.psi[s][c];
+        }
+    TMH_SCHED_FENCE();
+    load_t<P, 2, LAUX, LF>(d0, a, n, i);
+    TMH_SCHED_FENCE();
+    add_t<P, 1>(acc, d1, a, n);
+    TMH_SCHED_FENCE();
+    load_t<P, 3, LAUX, LF>(d1, a, n, i);
+    TMH_SCHED_FENCE();
+    add_t<P, 2>(acc, d0, a, n);
+    TMH_SCHED_FENCE();
+    load_t<P, 4, LAUX, LF>(d0, a, n, i);
+    TMH_SCHED_FENCE();
+    add_t<P, 3>(acc, d1, a, n);
+    TMH_SCHED_FENCE();
+    load_t<P, 5, LAUX, LF>(d1, a, n, i);
+    TMH_SCHED_FENCE();
+    add_t<P, 4>(acc, d0, a, n);
+    TMH_SCHED_FENCE();
+    load_t<P, 6, LAUX, LF>(d0, a, n, i);
+    TMH_SCHED_FENCE();
+    add_t<P, 5>(acc, d1, a, n);
+    TMH_SCHED_FENCE();
+    load_t<P, 7, LAUX, LF>(d1, a, n, i);
+    TMH_SCHED_FENCE();
+    add_t<P, 6>(acc, d0, a, n);
+    TMH_SCHED_FENCE();
+    add_t<P, 7>(acc, d1, a, n);
+}
+
+template <typename P, int MODE, int LF>
+__global__ void __launch_bounds__(kHopBlock) hop_tmarch_kernel(HopArgs<P> a) {
+    using R = real_t<P>;
+    if (a.done && *a.done) return;
+    if constexpr (MODE == 0) {
+        // CG step length from the preceding twist + norm hop (as hop_kernel)
+        if (a.apart && blockIdx.x == 0) {
+            double s = 0.0;
+            for (int k = threadIdx.x; k < a.napart; k += kHopBlock) s += a.apart[k];
+            s = block_sum<kHopBlock>(s);
+            if (threadIdx.x == 0) {
+                a.ascal[kPQ] = s;
+                a.ascal[kAlpha] = a.ascal[kRR] / s;
+            }
+            __syncthreads();
+        }
+    }
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int range = L / a.tm_nw, w = L - range * a.tm_nw;
+    const int slice = a.tm_slice, T = a.g.L[0], S = a.g.S;
+    const int jp = w * kHopBlock + threadIdx.x;  // pair index inside a slice (slice % kHopBlock == 0)
+    const int hz = a.g.L[3] >> 1;
+    const int row = jp / hz, zp = jp - row * hz;
+    const int y = row % a.g.L[2], x = row / a.g.L[2];
+    const int t0 = range * a.tm_steps;
+    cx<R> prev[4][3], cur[4][3];
+    load_psi<P>(prev, a.in, S, (t0 == 0 ? T - 1 : t0 - 1) * slice + jp);
+    load_psi<P>(cur, a.in, S, t0 * slice + jp);
+    __shared__ double wsum[kHopBlock / 64];
+    for (int st = 0; st < a.tm_steps; ++st) {
+        // The field addresses pass through an empty asm every step, so that
+        // the compiler rebuilds the ~170 buffer descriptors inside the step
+        // (a few scalar instructions each) instead of hoisting them out of
+        // the loop, where they would not fit in the scalar registers.
+        HopArgs<P> b = a;
+        __asm__ volatile("" : "+s"(b.in), "+s"(b.gout), "+s"(b.gin), "+s"(b.out), "+s"(b.aux));
+        if constexpr (MODE >= 3) __asm__ volatile("" : "+s"(b.rio), "+s"(b.xio), "+s"(b.pin));
+        const int t = t0 + st;
+        const int i = t * slice + jp;
+        int c[4];
+        c[0] = t;
+        c[1] = x;
+        c[2] = y;
+        c[3] = 2 * zp + ((t + x + y + a.pout) & 1);
+        const int lex = ((t * a.g.L[1] + x) * a.g.L[2] + y) * a.g.L[3] + c[3];
+        cx<R> acc[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[s][k] = mk<R>(0, 0);
+        const SiteNb n = site_neighbours(a.g, c, lex);
+        hop_site_tm<P, kLinkAux, LF>(acc, b, n, i, prev, cur);
+        const R alpha = MODE >= 3 ? (R)a.scal[kAlpha] : (R)0;
+        double nrm = 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const cx<R> cc = mk<R>(a.c_re[s >> 1], a.c_im[s >> 1]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int64_t comp = (int64_t)(3 * s + k) * S;
+                cx<R> o = cc * acc[s][k];
+                if constexpr (MODE >= 1)
+                    o += mk<R>(a.d_re[s >> 1], a.d_im[s >> 1]) * bload<P, out_aux<P>()>(b.aux + comp, S, i);
+                if constexpr (MODE == 2) nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+                if constexpr (MODE >= 3) {
+                    cx<R> r = bload<P>(b.rio + comp, S, i);
+                    r -= alpha * o;
+                    bstore<P>(b.rio + comp, S, i, r);
+                    nrm += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+                    if constexpr (MODE == 4) {
+                        cx<R> xv = bload<P>(b.xio + comp, S, i);
+                        xv += alpha * bload<P>(b.pin + comp, S, i);
+                        bstore<P>(b.xio + comp, S, i, xv);
+                    }
+                } else {
+                    bstore<P, out_aux<P>()>(b.out + comp, S, i, o);
+                }
+            }
+        }
+        if constexpr (MODE >= 2) {
+            // one partial per slice tile, at the index the one-site-per-lane
+            // kernel's blocks use: the sums keep their count and order
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+            if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = nrm;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double sum = 0.0;
+#pragma unroll
+                for (int k = 0; k < kHopBlock / 64; ++k) sum += wsum[k];
+                a.partial[t * a.tm_nw + w] = sum;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+int hop_tmarch_blocks(const Geo& g, int steps) { return g.Vh / kHopBlock / steps; }
+
 #ifndef TMH_HOP_LDS_PAD
 #define TMH_HOP_LDS_PAD 0
 #endif
@@ -157,8 +347,27 @@ static hipError_t launch_hop_lf(const HopArgs<P>& a, int mode, int nb, hipStream
     return hipGetLastError();
 }
 
+template <typename P, int LF>
+static hipError_t launch_tmarch_lf(const HopArgs<P>& a, int mode, int nb, hipStream_t stream) {
+    switch (mode) {
+        case 0: hipLaunchKernelGGL((hop_tmarch_kernel<P, 0, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        case 1: hipLaunchKernelGGL((hop_tmarch_kernel<P, 1, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        case 2: hipLaunchKernelGGL((hop_tmarch_kernel<P, 2, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        case 3: hipLaunchKernelGGL((hop_tmarch_kernel<P, 3, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+        default: hipLaunchKernelGGL((hop_tmarch_kernel<P, 4, LF>), dim3(nb), dim3(kHopBlock), 0, stream, a); break;
+    }
+    return hipGetLastError();
+}
+
 template <typename P>
 hipError_t launch_hop(const HopArgs<P>& a, int mode, hipStream_t stream) {
+    if (a.tm_steps > 0) {
+        // the host checked: tm_slice % kHopBlock == 0, tm_steps divides T,
+        // tm_nw * kHopBlock == tm_slice, T * tm_slice == Vh
+        const int nb = hop_tmarch_blocks(a.g, a.tm_steps);
+        if (nb == 0) return hipSuccess;
+        return a.lf ? launch_tmarch_lf<P, 1>(a, mode, nb, stream) : launch_tmarch_lf<P, 0>(a, mode, nb, stream);
+    }
     const int nb = hop_blocks(a.g);
     if (nb == 0) return hipSuccess;
     return a.lf ? launch_hop_lf<P, 1>(a, mode, nb, stream) : launch_hop_lf<P, 0>(a, mode, nb, stream);

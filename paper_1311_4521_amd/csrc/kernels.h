@@ -10,6 +10,8 @@ namespace tmh {
 
 // Traversal code of the hop kernels for one x-slab per XCD (see hop.hip).
 constexpr int kXSlab = -8;
+// Traversal codes of the t-marching hop kernel: kTMarch0 - steps.
+constexpr int kTMarch0 = -1024;
 
 // Arguments of one hopping-matrix launch on fields of storage precision P
 // (double, float or half_t), arithmetic in real_t<P>.
@@ -33,6 +35,9 @@ template <typename P> struct HopArgs {
     int pout;                         // parity of the output sites
     int lf;                           // link storage: 0 = 9 entries, 1 = two rows (12 reals)
     int xgroup, nyb, nt;              // traversal order (see hop.hip), xgroup = 0: eo order
+    int tm_steps;                     // > 0: t-marching kernel, each workgroup walks tm_steps time-slices
+    int tm_nw;                        //   workgroup tiles per time-slice (tm_slice / kHopThreads)
+    int tm_slice;                     //   sites per parity in one time-slice, LX LY LZ / 2
     R ph_re[4], ph_im[4];             // exp(i pi theta_mu)
     R c_re[2], c_im[2];               // coefficient of the hopping sum, upper/lower spins
     R d_re[2], d_im[2];               // coefficient of aux, upper/lower spins
@@ -55,6 +60,8 @@ struct ForceArgs {
 hipError_t launch_force(const ForceArgs& a, hipStream_t s);
 
 int hop_blocks(const Geo& g);
+// Workgroups of a t-marching hop launch (tm_steps > 0).
+int hop_tmarch_blocks(const Geo& g, int steps);
 constexpr int kHopThreads = 256;  // workgroup size of hop_kernel (TMH_HOP_BLOCK)
 template <typename R> hipError_t launch_hop(const HopArgs<R>& a, int mode, hipStream_t s);
 

@@ -45,6 +45,13 @@ NOALLOC_MAX_BYTES = 64 << 20  # TMH_NOALLOC_MAX_BYTES
 EO, OE = 0, 1
 XSLAB = -8  # traversal: one x-slab per XCD (TMH_TRAVERSAL_XSLAB)
 
+
+def TMARCH(steps: int) -> int:
+    """Traversal code of the t-marching hop kernel walking `steps`
+    time-slices per workgroup (TMH_TRAVERSAL_TMARCH)."""
+    return -1024 - int(steps)
+
+
 # precision codes: spinor word and link storage (F64_R12 / F32_R12 keep each
 # link as its first two rows, the third rebuilt in the kernels; SU(3) only)
 # F16 / F16_R12: FP16 storage with FP32 arithmetic
