@@ -222,6 +222,21 @@ def run_batch(args):
     hop_us = {sh: _time_us(lambda sh=sh: tm.hop_apply_mrhs(lat, "eo", Ym, G, Xm, kappa, theta, tm.F64, sh),
                            reps=3, warm=1) for sh in tm.tmhop.SHAPES.values()}
     del Xm, Ym
+    # the same in FP32: every shape, the matrix-core one among them
+    G32 = tm.gauge_import(lat, fieldgen.gauge_haar(lat.dims, seed), tm.F32)
+    Xs, Ys = lat.new_spinors(nrhs, tm.F32), lat.new_spinors(nrhs, tm.F32)
+    Xs.normal_()
+    hop_us32 = {sh: _time_us(lambda sh=sh: tm.hop_apply_mrhs(lat, "eo", Ys, G32, Xs, kappa, theta, tm.F32, sh),
+                             reps=3, warm=1) for sh in tm.tmhop.SHAPES.values()}
+    del G32, Xs, Ys
+    mfma = {}
+    for key, tab in (("f64", hop_us), ("f32", hop_us32)):
+        vec = {k: v for k, v in tab.items() if k != tm.tmhop.MFMA}
+        best = min(vec, key=vec.get)
+        mfma[key] = {"mfma_us": round(tab[tm.tmhop.MFMA], 1), "best_vector_us": round(vec[best], 1),
+                     "best_vector_shape": names[best],
+                     "mfma_over_vector": round(tab[tm.tmhop.MFMA] / vec[best], 3)}
+    log(f"12-RHS hop at 32^3x64, matrix cores against the best vector shape: {mfma}")
     mrhs_bytes = (1152 + nrhs * 384) * Vh
 
     def batched(sh):
@@ -289,7 +304,10 @@ def run_batch(args):
                                  "speedup_per_rhs": round(single_us * nrhs / multi_us, 3),
                                  "GBs_algorithmic": round(mrhs_bytes / (multi_us * 1e-6) / 1e9, 1),
                                  "bytes_per_site": 1152 + nrhs * 384,
-                                 "GFlops": round(1320 * nrhs * Vh / (multi_us * 1e-6) / 1e9, 1)},
+                                 "GFlops": round(1320 * nrhs * Vh / (multi_us * 1e-6) / 1e9, 1),
+                                 "us_by_shape_f64": {names[k]: round(v, 1) for k, v in hop_us.items()},
+                                 "us_by_shape_f32": {names[k]: round(v, 1) for k, v in hop_us32.items()},
+                                 "mfma": mfma},
     }
     print(json.dumps(line), flush=True)
 

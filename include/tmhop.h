@@ -247,8 +247,12 @@ tmh_status tmh_cg_solve(tmh_lattice* lat, void* x, const void* b, const void* ga
  * the right-hand sides of a workgroup share links through the caches; and
  * 5 = 128x2, 6 = 64x4, 7 = 128x4 with 2, 8 = 64x12, 9 = 128x6 with 3, and
  * 10 = 64x12, 11 = 128x4 with 4 right-hand sides per thread, which applies
- * each link it loads to all of them from registers.  -1 picks the autotuned
- * shape of the handle (tmh_autotune_mrhs) or a default. */
+ * each link it loads to all of them from registers; and 12 = 64x8 on the
+ * matrix cores: per term, the colour products of two sites and 8
+ * right-hand sides are three 16x16x4 MFMA products (FP64 or FP32) of the
+ * block-diagonal real form of the two links against the half-spinors,
+ * staged through LDS.  -1 picks the autotuned shape of the handle
+ * (tmh_autotune_mrhs) or a default. */
 typedef struct {
     tmh_lattice* lat;      /* every member on the same device, distinct handles */
     int nrhs;              /* right-hand sides (>= 1) */

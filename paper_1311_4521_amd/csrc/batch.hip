@@ -25,9 +25,9 @@
 namespace tmh {
 
 void batch_shape(int shape, int* sw, int* ry, int* nr) {
-    static const int SW[kNumShapes] = {4, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2};
-    static const int RY[kNumShapes] = {1, 2, 4, 4, 12, 1, 2, 2, 4, 2, 3, 1};
-    static const int NR[kNumShapes] = {1, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4};
+    static const int SW[kNumShapes] = {4, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1};
+    static const int RY[kNumShapes] = {1, 2, 4, 4, 12, 1, 2, 2, 4, 2, 3, 1, 8};
+    static const int NR[kNumShapes] = {1, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4, 1};
     *sw = SW[shape];
     *ry = RY[shape];
     *nr = NR[shape];
@@ -196,6 +196,246 @@ __global__ void __launch_bounds__(64 * SW * RY) batch_hop_kernel(BatchHopTable<R
     }
 }
 
+// ------------------------------------------------------------------ MFMA
+//
+// The same hop with the link products on the matrix cores (shape
+// kShapeMfma, FP64 and FP32).  Per term, the colour product of two sites is
+// one real block-diagonal product: rows (sigma, a, re/im) and columns
+// (sigma, b, re/im) of two 6x6 blocks [[Re U, -Im U], [Im U, Re U]] (or the
+// same for U^dagger), sigma = 0, 1 the site of the pair, against a 12 x 16
+// operand whose columns are (spin, rhs) of the half-spinors h of 2 spins x 8
+// right-hand sides: three 16x16x4 products (K = 12) per site pair and term.
+// Rows 12-15 of the result are zero.  An item is 64 sites x 8 right-hand
+// sides; wave w of its 8 waves holds sites 8w..8w+7, lane l the pair
+// (site 8w + l/8, rhs l%8), which projects the neighbour spinor to h, writes
+// it into the operand in LDS, and after the products reads its part of the
+// result back from LDS and rebuilds the lower spins (-DIR e_mu^dagger g).
+// Half of each 16x16 block and a quarter of its rows are zeros, so the
+// matrix cores do 16/6 times the floating-point work of the vector path;
+// both peaks are equal for FP64 on this chip.
+
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+    typedef double V4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V4 mma(double a, double b, V4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // Row of the result element that lane l holds as value v (the column is l % 16).
+    static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <> struct Mfma<float> {
+    typedef float V4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ V4 mma(float a, float b, V4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+constexpr int kMfmaWaves = 8;  // waves per item: 64 sites, 8 per wave
+constexpr int kMfmaRhs = 8;    // right-hand sides per item
+
+// Orders the LDS traffic of one wave (the lanes exchange data through LDS
+// within the wave only).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename R, int TT>
+__device__ __forceinline__ void mfma_term(cx<R> (&acc)[4][3], const BatchHopTask<R>& T, const SiteNb& n, int i,
+                                          bool in_range, bool live, int r, R* sBD, cx<R>* sU, int lane) {
+    using W = typename Word<R>::T;
+    constexpr int MU = TT / 2, DIR = (TT % 2 == 0) ? +1 : -1;
+    const int S = T.g.S;
+    const int pair = lane >> 4, sigma = (lane >> 3) & 1, rl = lane & 7, s8 = lane >> 3, e = lane & 7;
+    // 1. half-spinor of this lane's (neighbour site, rhs) with the boundary phase
+    cx<R> h[2][3];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) h[s][a] = mk<R>(0, 0);
+    if (live) {
+        const W* in = T.in + (int64_t)r * T.fstride;
+        cx<R> psi[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) psi[s][a] = bload<R>(in + (int64_t)(3 * s + a) * S, S, n.jn[TT]);
+        const bool wrap = (n.wrap >> TT) & 1u;
+        const cx<R> eta = wrap ? mk<R>(T.ph_re[MU], DIR > 0 ? T.ph_im[MU] : -T.ph_im[MU]) : mk<R>(1, 0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<R> e0, e1;
+            e_lower<R, MU>(psi[2][a], psi[3][a], e0, e1);
+            h[0][a] = (DIR > 0 ? psi[0][a] - e0 : psi[0][a] + e0) * eta;
+            h[1][a] = (DIR > 0 ? psi[1][a] - e1 : psi[1][a] + e1) * eta;
+        }
+    }
+    R* B = sBD + pair * 192;  // operand of this site pair: B[k][j], k = sigma*6 + b*2 + ri, j = spin*8 + rhs
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            B[(sigma * 6 + b * 2) * 16 + s * 8 + rl] = h[s][b].re;
+            B[(sigma * 6 + b * 2 + 1) * 16 + s * 8 + rl] = h[s][b].im;
+        }
+    // 2. the links of the wave's 8 sites: lane (site s8, entry e) loads entry e, lanes e = 0 also entry 8
+    {
+        const W* link = (DIR > 0 ? T.gout : T.gin) + (int64_t)MU * 9 * S;
+        const int jl = DIR > 0 ? i : n.jn[TT];
+        cx<R> u0 = mk<R>(0, 0), u8 = mk<R>(0, 0);
+        if (in_range) {
+            u0 = bload<R>(link + (int64_t)e * S, S, jl);
+            if (e == 0) u8 = bload<R>(link + (int64_t)8 * S, S, jl);
+        }
+        sU[s8 * 9 + e] = u0;
+        if (e == 0) sU[s8 * 9 + 8] = u8;
+    }
+    wave_lds_sync();
+    // 3. three products per site pair
+    typename Mfma<R>::V4 d[4];
+    const int arow = lane & 15;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        d[p] = typename Mfma<R>::V4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+            const int k = kk * 4 + (lane >> 4);
+            R a = 0;
+            if (arow < 12 && arow / 6 == k / 6) {
+                const int sr = arow / 6, ar = (arow % 6) >> 1, ro = arow & 1, bk = (k % 6) >> 1, ri = k & 1;
+                const cx<R> u = DIR > 0 ? sU[(2 * p + sr) * 9 + 3 * ar + bk] : sU[(2 * p + sr) * 9 + 3 * bk + ar];
+                // real form of u (forward) or conj(u) (backward, U^dagger entry (ar, bk) = conj U(bk, ar))
+                const R ui = DIR > 0 ? u.im : -u.im;
+                a = (ro == ri) ? u.re : (ro == 0 ? -ui : ui);
+            }
+            d[p] = Mfma<R>::mma(a, sBD[p * 192 + k * 16 + (lane & 15)], d[p]);
+        }
+    }
+    wave_lds_sync();
+    // 4. results back through LDS (the operand area is free now), then per lane
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sBD[p * 256 + Mfma<R>::row(lane, v) * 16 + (lane & 15)] = d[p][v];
+    wave_lds_sync();
+    if (live) {
+        const R* D = sBD + pair * 256;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<R> g[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+                g[s] = mk<R>(D[(sigma * 6 + a * 2) * 16 + s * 8 + rl], D[(sigma * 6 + a * 2 + 1) * 16 + s * 8 + rl]);
+            acc[0][a] += g[0];
+            acc[1][a] += g[1];
+            cx<R> f0, f1;
+            edag<R, MU>(g[0], g[1], f0, f1);
+            if constexpr (DIR > 0) {
+                acc[2][a] -= f0;
+                acc[3][a] -= f1;
+            } else {
+                acc[2][a] += f0;
+                acc[3][a] += f1;
+            }
+        }
+    }
+    wave_lds_sync();
+}
+
+template <typename R, int MODE>
+__global__ void __launch_bounds__(64 * kMfmaWaves) batch_hop_mfma_kernel(BatchHopTable<R> tasks, int nitems) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int sl = wv * 8 + (lane >> 3);  // site of this lane inside the 64-site tile
+    const int rl = lane & 7;
+    __shared__ R sBD[kMfmaWaves][4 * 256];
+    __shared__ cx<R> sU[kMfmaWaves][8 * 9];
+    __shared__ double red[kMfmaWaves][kMfmaRhs];
+    const XcdRange xr = xcd_range(nitems);
+    for (int it = xr.k; it < xr.count; it += xr.nper) {
+        const int item = xr.start + it;
+        const BatchHopTask<R>& T = tasks.t[find_task(tasks, item)];
+        const int local = item - T.item0;
+        const int ngroups = (T.nrhs + kMfmaRhs - 1) / kMfmaRhs;
+        const int tile = local / ngroups;
+        const int rhs0 = (local - tile * ngroups) * kMfmaRhs;
+        const int i = tile_site(tile, 64, T.xgroup, T.nyt, T.nt, T.g.L[1]) + sl;
+        const int r = rhs0 + rl;
+        const bool in_range = i < T.g.Vh;
+        const bool live = in_range && r < T.nrhs && !(T.flags && T.flags[2 * (T.sys0 + r)]);
+        SiteNb n;
+        n.wrap = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) n.jn[k] = 0;
+        if (in_range) {
+            int c[4], lex;
+            site_coords(T.g, i, T.pout, c, lex);
+            n = site_neighbours(T.g, c, lex);
+        }
+        cx<R> acc[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[s][k] = mk<R>(0, 0);
+        R* bd = sBD[wv];
+        cx<R>* su = sU[wv];
+        mfma_term<R, 0>(acc, T, n, i, in_range, live, r, bd, su, lane);
+        mfma_term<R, 1>(acc, T, n, i, in_range, live, r, bd, su, lane);
+        mfma_term<R, 2>(acc, T, n, i, in_range, live, r, bd, su, lane);
+        mfma_term<R, 3>(acc, T, n, i, in_range, live, r, bd, su, lane);
+        mfma_term<R, 4>(acc, T, n, i, in_range, live, r, bd, su, lane);
+        mfma_term<R, 5>(acc, T, n, i, in_range, live, r, bd, su, lane);
+        mfma_term<R, 6>(acc, T, n, i, in_range, live, r, bd, su, lane);
+        mfma_term<R, 7>(acc, T, n, i, in_range, live, r, bd, su, lane);
+        double nrm = 0.0;
+        if (live) {
+            const int S = T.g.S;
+            const int64_t fo = (int64_t)r * T.fstride;
+            typename Word<R>::T* out = T.out + fo;
+            const typename Word<R>::T* aux = T.aux + fo;
+            const R alpha = MODE == 3 ? (R)T.scal[(int64_t)(T.sys0 + r) * kNScal + kAlpha] : (R)0;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const cx<R> cc = mk<R>(T.c_re[s >> 1], T.c_im[s >> 1]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t comp = (int64_t)(3 * s + k) * S;
+                    cx<R> o = cc * acc[s][k];
+                    if constexpr (MODE >= 1)
+                        o += mk<R>(T.d_re[s >> 1], T.d_im[s >> 1]) * bload<R, out_aux<R>()>(aux + comp, S, i);
+                    if constexpr (MODE == 2) nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+                    if constexpr (MODE == 3) {
+                        cx<R> rv = bload<R>(T.rio + fo + comp, S, i);
+                        rv -= alpha * o;
+                        bstore<R>(T.rio + fo + comp, S, i, rv);
+                        cx<R> xv = bload<R>(T.xio + fo + comp, S, i);
+                        xv += alpha * bload<R>(T.pin + fo + comp, S, i);
+                        bstore<R>(T.xio + fo + comp, S, i, xv);
+                        nrm += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+                    } else {
+                        bstore<R, out_aux<R>()>(out + comp, S, i, o);
+                    }
+                }
+            }
+        }
+        if constexpr (MODE >= 2) {
+            // per right-hand side: lanes with the same l % 8, then the 8 waves in order
+#pragma unroll
+            for (int off = 8; off < 64; off <<= 1) nrm += __shfl_xor(nrm, off, 64);
+            if (lane < kMfmaRhs) red[wv][lane] = nrm;
+            __syncthreads();
+            if (threadIdx.x < kMfmaRhs && rhs0 + (int)threadIdx.x < T.nrhs) {
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < kMfmaWaves; ++w) v += red[w][threadIdx.x];
+                T.partial[(int64_t)(T.sys0 + rhs0 + threadIdx.x) * T.pstride + tile] = v;
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------- BLAS-1
 
 constexpr int kVecTile = kBlock;  // sites per item of the vector kernels
@@ -334,6 +574,7 @@ static const void* batch_hop_fn() {
 template <typename R, int MODE>
 static const void* batch_hop_sel(int shape) {
     switch (shape) {
+        case kShapeMfma: return reinterpret_cast<const void*>(&batch_hop_mfma_kernel<R, MODE>);
         case kShape4x1: return batch_hop_fn<R, MODE, 4, 1>();
         case kShape2x2: return batch_hop_fn<R, MODE, 2, 2>();
         case kShape1x4: return batch_hop_fn<R, MODE, 1, 4>();

@@ -158,7 +158,8 @@ enum BatchShapeId {
     kShape2x2r3 = 9,
     kShape1x3r4 = 10,
     kShape2x1r4 = 11,
-    kNumShapes = 12
+    kShapeMfma = 12,  // 64 sites x 8 right-hand sides, link products on the matrix cores
+    kNumShapes = 13
 };
 void batch_shape(int shape, int* sites_waves, int* wave_groups, int* rhs_per_thread);
 int batch_rhs_per_item(int shape);

@@ -13,6 +13,24 @@ counters taken on older code from current ones.
 
 ``stats`` turns a ``rocprofv3 --kernel-trace --stats`` kernel_stats.csv into
 a short markdown table.
+
+    python -m paper_1311_4521_amd.rocprof_summary requests READ_DIR WRITE_DIR OUT_MD SITES COPY_BYTES
+
+``requests`` reads two counter runs that bin the L2-to-memory requests by
+size: ``TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum
+TCC_EA0_RDREQ_sum`` and ``TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum
+TCC_EA0_RDREQ_DRAM_sum``.  Read bytes are 32, 64 and 128 times the binned
+counts, write bytes 64 times the 64-byte and 32 times the other write
+requests: no scale factor, and the streaming copy of known size in the same
+run checks them.  It writes a per-kernel table (bytes per launch and per
+site).
+
+    python -m paper_1311_4521_amd.rocprof_summary gaps TRACE_CSV PATTERN [LAST_N]
+
+``gaps`` measures, from a kernel trace, how much of the wall time of the
+last LAST_N dispatches whose names contain PATTERN (default: all of them)
+lies between kernels rather than inside one: the launch-boundary share of a
+stretch of back-to-back launches.
 """
 
 from __future__ import annotations
@@ -128,6 +146,69 @@ def stats(stats_csv, out_md):
         fh.write("\n".join(lines) + "\n")
 
 
+RD_BINS = (("TCC_EA0_RDREQ_32B_sum", 32), ("TCC_EA0_RDREQ_64B_sum", 64), ("TCC_EA0_RDREQ_128B_sum", 128))
+
+
+def _mean_per_kernel(rows, counter):
+    acc = {}
+    for r in rows:
+        if r["Counter_Name"] == counter:
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+
+
+def requests(read_dir, write_dir, out_md, sites, copy_bytes, command=""):
+    """Bytes per launch from the size-binned request counters (see module
+    docstring).  Returns {kernel: (read bytes, write bytes, launches)}."""
+    rrows, wrows = _rows(read_dir), _rows(write_dir)
+    rd = {}
+    counts = {}
+    for counter, size in RD_BINS:
+        m, n = _mean_per_kernel(rrows, counter)
+        for k, v in m.items():
+            rd[k] = rd.get(k, 0.0) + size * v
+            counts[k] = n[k]
+    wall, _ = _mean_per_kernel(wrows, "TCC_EA0_WRREQ_sum")
+    w64, _ = _mean_per_kernel(wrows, "TCC_EA0_WRREQ_64B_sum")
+    dram, _ = _mean_per_kernel(wrows, "TCC_EA0_RDREQ_DRAM_sum")
+    wr = {k: 64.0 * w64.get(k, 0.0) + 32.0 * (v - w64.get(k, 0.0)) for k, v in wall.items()}
+    copy = [k for k in rd if COPY in k]
+    if not copy:
+        raise SystemExit("no streaming copy in the counter output")
+    cr, cw = rd[copy[0]], wr.get(copy[0], 0.0)
+    res = {k: (rd[k], wr.get(k, 0.0), counts[k], dram.get(k)) for k in rd if "tmh::" in k}
+    lines = [f"Counters binned by request size: read bytes = 32 n32 + 64 n64 + 128 n128, write bytes = "
+             f"64 n64 + 32 (n - n64), no scale factor.  Check: the streaming copy of {copy_bytes:,.0f} bytes "
+             f"reads {cr:,.0f} and writes {cw:,.0f} bytes per launch ({cr / copy_bytes:.4f} / "
+             f"{cw / copy_bytes:.4f}).", "",
+             "| kernel | launches | read MB | write MB | read B/site | write B/site | DRAM read requests |",
+             "|---|---|---|---|---|---|---|"]
+    for k, (r, w, n, d) in sorted(res.items(), key=lambda kv: -kv[1][0]):
+        short = k if len(k) <= 90 else k[:87] + "..."
+        lines.append(f"| `{short}` | {n} | {r / 1e6:.1f} | {w / 1e6:.1f} | {r / sites:.1f} | {w / sites:.1f} | "
+                     f"{'' if d is None else f'{d:,.0f}'} |")
+    with open(out_md, "w") as fh:
+        if command:
+            fh.write(command.rstrip() + "\n\n")
+        fh.write("\n".join(lines) + "\n")
+    return res
+
+
+def gaps(trace_csv, pattern, last_n=None):
+    """(kernel busy ns, wall ns, dispatches) over the last `last_n` dispatches
+    whose names contain `pattern`, taken as one back-to-back stretch."""
+    with open(trace_csv) as fh:
+        rows = [r for r in csv.DictReader(fh) if pattern in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    if last_n:
+        rows = rows[-int(last_n):]
+    if not rows:
+        raise SystemExit(f"no dispatch matches {pattern!r}")
+    busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows)
+    wall = int(rows[-1]["End_Timestamp"]) - int(rows[0]["Start_Timestamp"])
+    return busy, wall, len(rows)
+
+
 if __name__ == "__main__":
     cmd = sys.argv[1]
     if cmd == "traffic":
@@ -139,5 +220,12 @@ if __name__ == "__main__":
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], **extra), indent=1))
     elif cmd == "stats":
         stats(sys.argv[2], sys.argv[3])
+    elif cmd == "requests":
+        requests(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), float(sys.argv[6]),
+                 command=os.environ.get("TMH_PROFILE_COMMAND", ""))
+    elif cmd == "gaps":
+        b, wl, n = gaps(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) > 4 else None)
+        print(f"{n} dispatches: kernels busy {b / 1e6:.3f} ms of {wl / 1e6:.3f} ms wall, "
+              f"between kernels {100.0 * (wl - b) / wl:.1f} %")
     else:
         raise SystemExit(__doc__)

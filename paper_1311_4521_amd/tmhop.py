@@ -369,9 +369,11 @@ def solve_full(lat: Lattice, x_even, x_odd, b_even, b_odd, gauge, kappa, mu, the
 
 
 # tile shapes: sites x right-hand sides per workgroup; "/rN": each thread
-# applies every link it loads to N right-hand sides
+# applies every link it loads to N right-hand sides; "/mfma": the link
+# products run on the matrix cores
 SHAPES = {"256x1": 0, "128x2": 1, "64x4": 2, "128x4": 3, "64x12": 4, "128x2/r2": 5, "64x4/r2": 6,
-          "128x4/r2": 7, "64x12/r3": 8, "128x6/r3": 9, "64x12/r4": 10, "128x4/r4": 11}
+          "128x4/r2": 7, "64x12/r3": 8, "128x6/r3": 9, "64x12/r4": 10, "128x4/r4": 11, "64x8/mfma": 12}
+MFMA = 12
 
 
 def _expect_multi(t, lat, prec, nrhs):

@@ -68,3 +68,47 @@ def test_stats_counts_early_exits(tmp_path):
     assert float(dom[7]) == pytest.approx(303.33, abs=0.01)
     cp = [l for l in lines if "stream_copy" in l][0].split("|")
     assert cp[6].strip() == "0" and float(cp[7]) == pytest.approx(100.0)
+
+
+def write_multi(path, rows):
+    path.mkdir()
+    with open(path / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for k, (name, counter, value) in enumerate(rows):
+            w.writerow({"Dispatch_Id": k, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value})
+
+
+def test_requests_bins_bytes_by_size(tmp_path):
+    """Read bytes are 32/64/128 times the binned counts, write bytes 64 times
+    the 64-byte requests plus 32 times the rest; the copy kernel checks them."""
+    copy_bytes = 128 * 1000
+    write_multi(tmp_path / "r", [
+        (COPY, "TCC_EA0_RDREQ_128B_sum", 1000), (COPY, "TCC_EA0_RDREQ_64B_sum", 0),
+        (COPY, "TCC_EA0_RDREQ_32B_sum", 0),
+        (DOM, "TCC_EA0_RDREQ_128B_sum", 10), (DOM, "TCC_EA0_RDREQ_64B_sum", 3),
+        (DOM, "TCC_EA0_RDREQ_32B_sum", 2),
+        (DOM, "TCC_EA0_RDREQ_128B_sum", 20), (DOM, "TCC_EA0_RDREQ_64B_sum", 5),
+        (DOM, "TCC_EA0_RDREQ_32B_sum", 0)])
+    write_multi(tmp_path / "w", [
+        (COPY, "TCC_EA0_WRREQ_sum", 2000), (COPY, "TCC_EA0_WRREQ_64B_sum", 2000),
+        (DOM, "TCC_EA0_WRREQ_sum", 7), (DOM, "TCC_EA0_WRREQ_64B_sum", 4), (DOM, "TCC_EA0_RDREQ_DRAM_sum", 9)])
+    out = tmp_path / "req.md"
+    res = rs.requests(str(tmp_path / "r"), str(tmp_path / "w"), str(out), 2.0, copy_bytes)
+    rd, wr, n, dram = res[DOM]
+    assert rd == pytest.approx(128 * 15 + 64 * 4 + 32 * 1) and n == 2
+    assert wr == pytest.approx(64 * 4 + 32 * 3) and dram == pytest.approx(9)
+    text = open(out).read()
+    assert "(1.0000 / 1.0000)" in text and "hop_kernel" in text
+
+
+def test_gaps_share_between_kernels(tmp_path):
+    p = tmp_path / "t_kernel_trace.csv"
+    with open(p, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for name, s, e in (("batch_hop_kernel", 0, 100), ("other", 150, 160), ("batch_hop_kernel", 200, 290),
+                           ("batch_vec_kernel", 300, 340), ("batch_hop_kernel", 350, 450)):
+            w.writerow({"Kernel_Name": name, "Start_Timestamp": s, "End_Timestamp": e})
+    assert rs.gaps(str(p), "batch_") == (330, 450, 4)
+    assert rs.gaps(str(p), "batch_", 2) == (140, 150, 2)
