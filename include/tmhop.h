@@ -251,8 +251,14 @@ tmh_status tmh_cg_solve(tmh_lattice* lat, void* x, const void* b, const void* ga
  * matrix cores: per term, the colour products of two sites and 8
  * right-hand sides are three 16x16x4 MFMA products (FP64 or FP32) of the
  * block-diagonal real form of the two links against the half-spinors,
- * staged through LDS.  -1 picks the autotuned shape of the handle
- * (tmh_autotune_mrhs) or a default. */
+ * staged through LDS; 13 and 14 = t-march: a workgroup walks a range of
+ * time-slices for one tile of 256 site pairs and one right-hand side,
+ * keeping the projected time neighbours of its sites in registers (the
+ * workgroups of a tile for all right-hand sides run together, sharing its
+ * links), 14 with the loads of the next term issued before each term;
+ * lattices whose LX*LY*LZ/2 is not a multiple of 256 get
+ * TMH_ERR_UNSUPPORTED for these two.  -1 picks the autotuned shape of the
+ * handle (tmh_autotune_mrhs) or a default. */
 typedef struct {
     tmh_lattice* lat;      /* every member on the same device, distinct handles */
     int nrhs;              /* right-hand sides (>= 1) */

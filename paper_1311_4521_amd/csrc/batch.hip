@@ -25,9 +25,9 @@
 namespace tmh {
 
 void batch_shape(int shape, int* sw, int* ry, int* nr) {
-    static const int SW[kNumShapes] = {4, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1};
-    static const int RY[kNumShapes] = {1, 2, 4, 4, 12, 1, 2, 2, 4, 2, 3, 1, 8};
-    static const int NR[kNumShapes] = {1, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4, 1};
+    static const int SW[kNumShapes] = {4, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 4, 4};
+    static const int RY[kNumShapes] = {1, 2, 4, 4, 12, 1, 2, 2, 4, 2, 3, 1, 8, 1, 1};
+    static const int NR[kNumShapes] = {1, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4, 1, 1, 1};
     *sw = SW[shape];
     *ry = RY[shape];
     *nr = NR[shape];
@@ -436,6 +436,212 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) batch_hop_mfma_kernel(BatchHo
     }
 }
 
+// ------------------------------------------------------------- t-march
+//
+// The multi-right-hand-side form of the t-marching hop (hop.hip): a
+// workgroup owns one tile of 256 site pairs of a time-slice, one right-hand
+// side, and a range of tm_steps time-slices, which it walks.  A thread keeps
+// the projections (1 + gamma_0) psi of its pair's input sites at t - 1 and t
+// (the backward time term two and one steps later) in registers and loads
+// each input site once, as the forward time neighbour.  The workgroups of a
+// tile for all right-hand sides are consecutive, so an XCD works on a few
+// tiles for all right-hand sides at once: the links they share are read
+// once, and one step's new data (the next slice of those tiles for every
+// right-hand side and their links) stays small against the L2, so the
+// spatial neighbours read in the next step are still there.
+
+// Workgroups of the t-march are dealt to XCDs so that each XCD takes one
+// contiguous eighth of every task (its tiles for all right-hand sides), task
+// after task: the XCDs get equal shares of lattices whose workgroups walk
+// different numbers of time-slices.  Hardware workgroup b runs on XCD b % 8
+// as its (b / 8)-th; returns the task and its local workgroup index, or
+// false past the end of the XCD's list.
+template <typename R>
+__device__ __forceinline__ bool tmarch_block(const BatchHopTable<R>& tasks, int& ti, int& local) {
+    const int x = blockIdx.x % kXcds;
+    int j = blockIdx.x / kXcds;
+    for (ti = 0; ti < tasks.ntasks; ++ti) {
+        const BatchHopTask<R>& T = tasks.t[ti];
+        const int nb = batch_tmarch_blocks(T.g.L[0], T.tm_steps, T.tm_nw, T.nrhs);
+        const int q = nb / kXcds, m = nb % kXcds;
+        const int cnt = q + (x < m ? 1 : 0);
+        if (j < cnt) {
+            local = x * q + (x < m ? x : m) + j;
+            return true;
+        }
+        j -= cnt;
+    }
+    return false;
+}
+
+template <typename R, int MODE, bool PIPE>
+__global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> tasks) {
+    using W = typename Word<R>::T;
+    int ti, local;
+    if (!tmarch_block(tasks, ti, local)) return;
+    const BatchHopTask<R>& T = tasks.t[ti];
+    const int rhs = local % T.nrhs, tmp = local / T.nrhs;
+    const int w = tmp % T.tm_nw, range = tmp / T.tm_nw;
+    if (T.flags && T.flags[2 * (T.sys0 + rhs)]) return;
+    const int slice = T.tm_slice, LT = T.g.L[0], S = T.g.S;
+    const int jp = w * 256 + threadIdx.x;
+    const int hz = T.g.L[3] >> 1;
+    const int row = jp / hz, zp = jp - row * hz;
+    const int y = row % T.g.L[2], x = row / T.g.L[2];
+    const int t0 = range * T.tm_steps;
+    const int64_t fo = (int64_t)rhs * T.fstride;
+    HopArgs<R> a;
+    a.in = T.in + fo;
+    a.gout = T.gout;
+    a.gin = T.gin;
+    a.g = T.g;
+    a.pout = T.pout;
+    a.lf = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        a.ph_re[m] = T.ph_re[m];
+        a.ph_im[m] = T.ph_im[m];
+    }
+    cx<R> hprev[2][3], hcur[2][3];
+    {
+        cx<R> psi[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                psi[s][c] = bload<R>(a.in + (int64_t)(3 * s + c) * S, S, (t0 == 0 ? LT - 1 : t0 - 1) * slice + jp);
+        project<R, 0, -1>(hprev, psi);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) psi[s][c] = bload<R>(a.in + (int64_t)(3 * s + c) * S, S, t0 * slice + jp);
+        project<R, 0, -1>(hcur, psi);
+    }
+    const R alpha = MODE == 3 ? (R)T.scal[(int64_t)(T.sys0 + rhs) * kNScal + kAlpha] : (R)0;
+    __shared__ double wsum[4];
+    for (int st = 0; st < T.tm_steps; ++st) {
+        HopArgs<R> b = a;
+        // rebuilt descriptors every step (see hop_tmarch_kernel)
+        __asm__ volatile("" : "+s"(b.in), "+s"(b.gout), "+s"(b.gin));
+        const int t = t0 + st;
+        const int i = t * slice + jp;
+        int c[4];
+        c[0] = t;
+        c[1] = x;
+        c[2] = y;
+        c[3] = 2 * zp + ((t + x + y + T.pout) & 1);
+        const int lex = ((t * T.g.L[1] + x) * T.g.L[2] + y) * T.g.L[3] + c[3];
+        const SiteNb n = site_neighbours(T.g, c, lex);
+        cx<R> acc[4][3];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[s][k] = mk<R>(0, 0);
+        {
+            // forward time term from memory; its backward projection joins the ring
+            TermData<R> d;
+            load_t<R, 0, 0, 0>(d, b, n, i);
+            cx<R> hf[2][3], hn[2][3];
+            project<R, 0, +1>(hf, d.psi);
+            project<R, 0, -1>(hn, d.psi);
+            add_term_h<R, 0, +1>(acc, hf, d.u, (n.wrap >> 0) & 1u, mk<R>(b.ph_re[0], b.ph_im[0]));
+            // backward time term from the ring
+            TermData<R> e;
+            {
+                const typename Word<R>::T* link = b.gin;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) e.u[k / 3][k % 3] = bload<R>(link + (int64_t)k * S, S, n.jn[1]);
+            }
+            add_term_h<R, 0, -1>(acc, hprev, e.u, (n.wrap >> 1) & 1u, mk<R>(b.ph_re[0], -b.ph_im[0]));
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    hprev[s][k] = hcur[s][k];
+                    hcur[s][k] = hn[s][k];
+                }
+        }
+        TMH_SCHED_FENCE();
+        if constexpr (PIPE) {
+            TermData<R> d0, d1;
+            load_t<R, 2, 0, 0>(d0, b, n, i);
+            TMH_SCHED_FENCE();
+            load_t<R, 3, 0, 0>(d1, b, n, i);
+            TMH_SCHED_FENCE();
+            add_t<R, 2>(acc, d0, b, n);
+            TMH_SCHED_FENCE();
+            load_t<R, 4, 0, 0>(d0, b, n, i);
+            TMH_SCHED_FENCE();
+            add_t<R, 3>(acc, d1, b, n);
+            TMH_SCHED_FENCE();
+            load_t<R, 5, 0, 0>(d1, b, n, i);
+            TMH_SCHED_FENCE();
+            add_t<R, 4>(acc, d0, b, n);
+            TMH_SCHED_FENCE();
+            load_t<R, 6, 0, 0>(d0, b, n, i);
+            TMH_SCHED_FENCE();
+            add_t<R, 5>(acc, d1, b, n);
+            TMH_SCHED_FENCE();
+            load_t<R, 7, 0, 0>(d1, b, n, i);
+            TMH_SCHED_FENCE();
+            add_t<R, 6>(acc, d0, b, n);
+            TMH_SCHED_FENCE();
+            add_t<R, 7>(acc, d1, b, n);
+        } else {
+            TermData<R> d;
+#define TMH_TM_TERM(TT)              \
+    load_t<R, TT, 0, 0>(d, b, n, i); \
+    add_t<R, TT>(acc, d, b, n);      \
+    TMH_SCHED_FENCE();
+            TMH_TM_TERM(2) TMH_TM_TERM(3) TMH_TM_TERM(4) TMH_TM_TERM(5) TMH_TM_TERM(6) TMH_TM_TERM(7)
+#undef TMH_TM_TERM
+        }
+        W* out = T.out + fo;
+        const W* aux = T.aux + fo;
+        W* rio = T.rio + fo;
+        W* xio = T.xio + fo;
+        const W* pin = T.pin + fo;
+        __asm__ volatile("" : "+s"(out), "+s"(aux));
+        if constexpr (MODE == 3) __asm__ volatile("" : "+s"(rio), "+s"(xio), "+s"(pin));
+        double nrm = 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const cx<R> cc = mk<R>(T.c_re[s >> 1], T.c_im[s >> 1]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int64_t comp = (int64_t)(3 * s + k) * S;
+                cx<R> o = cc * acc[s][k];
+                if constexpr (MODE >= 1)
+                    o += mk<R>(T.d_re[s >> 1], T.d_im[s >> 1]) * bload<R, out_aux<R>()>(aux + comp, S, i);
+                if constexpr (MODE == 2) nrm += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+                if constexpr (MODE == 3) {
+                    cx<R> rv = bload<R>(rio + comp, S, i);
+                    rv -= alpha * o;
+                    bstore<R>(rio + comp, S, i, rv);
+                    cx<R> xv = bload<R>(xio + comp, S, i);
+                    xv += alpha * bload<R>(pin + comp, S, i);
+                    bstore<R>(xio + comp, S, i, xv);
+                    nrm += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+                } else {
+                    bstore<R, out_aux<R>()>(out + comp, S, i, o);
+                }
+            }
+        }
+        if constexpr (MODE >= 2) {
+            // one partial per (system, slice tile), as the tiles of 256 sites
+            // of the other shapes
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
+            if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = nrm;
+            __syncthreads();
+            if (threadIdx.x == 0)
+                T.partial[(int64_t)(T.sys0 + rhs) * T.pstride + t * T.tm_nw + w] =
+                    wsum[0] + wsum[1] + wsum[2] + wsum[3];
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------- BLAS-1
 
 constexpr int kVecTile = kBlock;  // sites per item of the vector kernels
@@ -632,8 +838,30 @@ static int persistent_grid(const void* fn, int threads, int nitems) {
     return grid < kXcds ? kXcds : grid;
 }
 
+template <typename R, bool PIPE>
+static hipError_t launch_tmarch(const BatchHopTable<R>& tab, int mode, hipStream_t s) {
+    // every XCD's list holds ceil(nb / 8) workgroups of each task at most
+    int per_xcd = 0;
+    for (int k = 0; k < tab.ntasks; ++k)
+        per_xcd += (batch_tmarch_blocks(tab.t[k].g.L[0], tab.t[k].tm_steps, tab.t[k].tm_nw, tab.t[k].nrhs) +
+                    kXcds - 1) / kXcds;
+    const int grid = per_xcd * kXcds;
+    if (grid == 0) return hipSuccess;
+    switch (mode) {
+        case 0: hipLaunchKernelGGL((batch_tmarch_kernel<R, 0, PIPE>), dim3(grid), dim3(256), 0, s, tab); break;
+        case 1: hipLaunchKernelGGL((batch_tmarch_kernel<R, 1, PIPE>), dim3(grid), dim3(256), 0, s, tab); break;
+        case 2: hipLaunchKernelGGL((batch_tmarch_kernel<R, 2, PIPE>), dim3(grid), dim3(256), 0, s, tab); break;
+        default: hipLaunchKernelGGL((batch_tmarch_kernel<R, 3, PIPE>), dim3(grid), dim3(256), 0, s, tab); break;
+    }
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_batch_hop(const BatchHopTable<R>& tasks, int nitems, int shape, int mode, hipStream_t s) {
+    // t-march shapes: the host has set tm_steps, tm_nw and tm_slice of every
+    // task (slices of whole tiles of 256 pairs, steps dividing T)
+    if (shape == kShapeTMarch) return launch_tmarch<R, false>(tasks, mode, s);
+    if (shape == kShapeTMarchPipe) return launch_tmarch<R, true>(tasks, mode, s);
     if (nitems == 0) return hipSuccess;
     int sw, ry, nr;
     batch_shape(shape, &sw, &ry, &nr);
@@ -679,6 +907,7 @@ hipError_t launch_batch_scalar(int op, int nsys, const BatchSysTable& sys, doubl
 int batch_vec_tiles(int Vh) { return (Vh + kVecTile - 1) / kVecTile; }
 
 void batch_prepare(int shape) {
+    if (batch_is_tmarch(shape)) return;  // not persistent: nothing to size
     int sw, ry, nr;
     batch_shape(shape, &sw, &ry, &nr);
     for (int mode = 0; mode < 4; ++mode) {

@@ -177,7 +177,6 @@ __device__ __forceinline__ void load_link_t(TermData<real_t<P>>& d, const HopArg
     const int jl = T % 2 == 0 ? i : n.jn[T];
 #pragma unroll
     for (int k = 0; k < NC; ++k) d.u[k / 3][k % 3] = bload<P, LAUX>(link + (int64_t)k * S, S, jl);
-    if constexpr (LF == 1) third_row<real_t<P>>(d.u);
 }
 
 // The 8 terms of one output site in the t-march: term 0 (forward t) loads
@@ -196,7 +195,7 @@ __device__ __forceinline__ void hop_site_tm(cx<real_t<P>> (&acc)[4][3], const Ho
 #pragma unroll
         for (int c = 0; c < 3; ++c) d1.psi[s][c] = prev[s][c];
     TMH_SCHED_FENCE();
-    add_t<P, 0>(acc, d0, a, n);
+    add_t<P, 0, LF>(acc, d0, a, n);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -207,29 +206,29 @@ __device__ __forceinline__ void hop_site_tm(cx<real_t<P>> (&acc)[4][3], const Ho
     TMH_SCHED_FENCE();
     load_t<P, 2, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 1>(acc, d1, a, n);
+    add_t<P, 1, LF>(acc, d1, a, n);
     TMH_SCHED_FENCE();
     load_t<P, 3, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 2>(acc, d0, a, n);
+    add_t<P, 2, LF>(acc, d0, a, n);
     TMH_SCHED_FENCE();
     load_t<P, 4, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 3>(acc, d1, a, n);
+    add_t<P, 3, LF>(acc, d1, a, n);
     TMH_SCHED_FENCE();
     load_t<P, 5, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 4>(acc, d0, a, n);
+    add_t<P, 4, LF>(acc, d0, a, n);
     TMH_SCHED_FENCE();
     load_t<P, 6, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 5>(acc, d1, a, n);
+    add_t<P, 5, LF>(acc, d1, a, n);
     TMH_SCHED_FENCE();
     load_t<P, 7, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 6>(acc, d0, a, n);
+    add_t<P, 6, LF>(acc, d0, a, n);
     TMH_SCHED_FENCE();
-    add_t<P, 7>(acc, d1, a, n);
+    add_t<P, 7, LF>(acc, d1, a, n);
 }
 
 template <typename P, int MODE, int LF>

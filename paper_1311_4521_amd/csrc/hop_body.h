@@ -94,27 +94,46 @@ __device__ __forceinline__ void load_term(TermData<real_t<P>>& d, const typename
         for (int a = 0; a < 3; ++a) d.psi[s][a] = bload<P>(in + (int64_t)(3 * s + a) * S, S, jn);
 #pragma unroll
     for (int k = 0; k < link_comps<LF>(); ++k) d.u[k / 3][k % 3] = bload<P, LAUX>(link + (int64_t)k * S, S, jl);
-    if constexpr (LF == 1) third_row<real_t<P>>(d.u);
+    // two-row links: the third row is rebuilt where the term is computed
+    // (add_t), so that the loads of a term can be issued ahead of it
 }
+
+// Spin projection of one term: the half-spinor h = psi_up - DIR e_mu psi_dn
+// that (1 - DIR gamma_mu) leaves independent.
+template <typename R, int MU, int DIR>
+__device__ __forceinline__ void project(cx<R> (&h)[2][3], const cx<R> (&psi)[4][3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<R> e0, e1;
+        e_lower<R, MU>(psi[2][a], psi[3][a], e0, e1);
+        if constexpr (DIR > 0) {
+            h[0][a] = psi[0][a] - e0;
+            h[1][a] = psi[1][a] - e1;
+        } else {
+            h[0][a] = psi[0][a] + e0;
+            h[1][a] = psi[1][a] + e1;
+        }
+    }
+}
+
+// A term from its projected half-spinor h (taken by value: the boundary
+// phase is applied to it here) and its link.
+template <typename R, int MU, int DIR>
+__device__ __forceinline__ void add_term_h(cx<R> (&acc)[4][3], cx<R> h[2][3], const cx<R> (&u)[3][3], bool wrap,
+                                           cx<R> ph);
 
 // One of the 8 terms: DIR = +1 adds (1 - gamma_mu) U_mu(x) psi(x+mu),
 // DIR = -1 adds (1 + gamma_mu) U_mu(x-mu)^dagger psi(x-mu).
 template <typename R, int MU, int DIR>
 __device__ __forceinline__ void add_term(cx<R> (&acc)[4][3], const TermData<R>& d, bool wrap, cx<R> ph) {
-    // half-spinor h = psi_up - DIR e_mu psi_dn
     cx<R> h[2][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        cx<R> e0, e1;
-        e_lower<R, MU>(d.psi[2][a], d.psi[3][a], e0, e1);
-        if constexpr (DIR > 0) {
-            h[0][a] = d.psi[0][a] - e0;
-            h[1][a] = d.psi[1][a] - e1;
-        } else {
-            h[0][a] = d.psi[0][a] + e0;
-            h[1][a] = d.psi[1][a] + e1;
-        }
-    }
+    project<R, MU, DIR>(h, d.psi);
+    add_term_h<R, MU, DIR>(acc, h, d.u, wrap, ph);
+}
+
+template <typename R, int MU, int DIR>
+__device__ __forceinline__ void add_term_h(cx<R> (&acc)[4][3], cx<R> h[2][3], const cx<R> (&u)[3][3], bool wrap,
+                                           cx<R> ph) {
     // boundary phase, branch-free so that each term stays one basic block
     const cx<R> eta = wrap ? ph : mk<R>(1, 0);
 #pragma unroll
@@ -128,9 +147,9 @@ __device__ __forceinline__ void add_term(cx<R> (&acc)[4][3], const TermData<R>& 
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             if constexpr (DIR > 0)
-                g[s][a] = d.u[a][0] * h[s][0] + d.u[a][1] * h[s][1] + d.u[a][2] * h[s][2];
+                g[s][a] = u[a][0] * h[s][0] + u[a][1] * h[s][1] + u[a][2] * h[s][2];
             else
-                g[s][a] = cmul(d.u[0][a], h[s][0]) + cmul(d.u[1][a], h[s][1]) + cmul(d.u[2][a], h[s][2]);
+                g[s][a] = cmul(u[0][a], h[s][0]) + cmul(u[1][a], h[s][1]) + cmul(u[2][a], h[s][2]);
         }
     // upper spins take g, lower spins take -DIR e_mu^dagger g
 #pragma unroll
@@ -185,11 +204,12 @@ __device__ __forceinline__ void load_t(TermData<real_t<P>>& d, const HopArgs<P>&
         load_term<P, LAUX, LF>(d, a.in, a.gin + (int64_t)MU * NC * a.g.S, a.g.S, n.jn[T], n.jn[T]);
 }
 
-template <typename P, int T>
-__device__ __forceinline__ void add_t(cx<real_t<P>> (&acc)[4][3], const TermData<real_t<P>>& d,
-                                      const HopArgs<P>& a, const SiteNb& n) {
+template <typename P, int T, int LF = 0>
+__device__ __forceinline__ void add_t(cx<real_t<P>> (&acc)[4][3], TermData<real_t<P>>& d, const HopArgs<P>& a,
+                                      const SiteNb& n) {
     using R = real_t<P>;
     constexpr int MU = T / 2;
+    if constexpr (LF == 1) third_row<R>(d.u);
     const bool wrap = (n.wrap >> T) & 1u;
     if constexpr (T % 2 == 0)
         add_term<R, MU, +1>(acc, d, wrap, mk<R>(a.ph_re[MU], a.ph_im[MU]));
@@ -216,38 +236,38 @@ __device__ __forceinline__ void hop_site(cx<real_t<P>> (&acc)[4][3], const HopAr
     TMH_SCHED_FENCE();
     load_t<P, 1, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 0>(acc, d0, a, n);
+    add_t<P, 0, LF>(acc, d0, a, n);
     TMH_SCHED_FENCE();
     load_t<P, 2, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 1>(acc, d1, a, n);
+    add_t<P, 1, LF>(acc, d1, a, n);
     TMH_SCHED_FENCE();
     load_t<P, 3, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 2>(acc, d0, a, n);
+    add_t<P, 2, LF>(acc, d0, a, n);
     TMH_SCHED_FENCE();
     load_t<P, 4, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 3>(acc, d1, a, n);
+    add_t<P, 3, LF>(acc, d1, a, n);
     TMH_SCHED_FENCE();
     load_t<P, 5, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 4>(acc, d0, a, n);
+    add_t<P, 4, LF>(acc, d0, a, n);
     TMH_SCHED_FENCE();
     load_t<P, 6, LAUX, LF>(d0, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 5>(acc, d1, a, n);
+    add_t<P, 5, LF>(acc, d1, a, n);
     TMH_SCHED_FENCE();
     load_t<P, 7, LAUX, LF>(d1, a, n, i);
     TMH_SCHED_FENCE();
-    add_t<P, 6>(acc, d0, a, n);
+    add_t<P, 6, LF>(acc, d0, a, n);
     TMH_SCHED_FENCE();
-    add_t<P, 7>(acc, d1, a, n);
+    add_t<P, 7, LF>(acc, d1, a, n);
     } else {
     TermData<R> d;
 #define TMH_TERM(T)              \
     load_t<P, T, LAUX, LF>(d, a, n, i);    \
-    add_t<P, T>(acc, d, a, n);   \
+    add_t<P, T, LF>(acc, d, a, n);   \
     TMH_SCHED_FENCE();
     TMH_TERM(0) TMH_TERM(1) TMH_TERM(2) TMH_TERM(3) TMH_TERM(4) TMH_TERM(5) TMH_TERM(6) TMH_TERM(7)
 #undef TMH_TERM

@@ -159,9 +159,14 @@ enum BatchShapeId {
     kShape1x3r4 = 10,
     kShape2x1r4 = 11,
     kShapeMfma = 12,  // 64 sites x 8 right-hand sides, link products on the matrix cores
-    kNumShapes = 13
+    kShapeTMarch = 13,      // t-march: a workgroup walks time-slices for one tile and one rhs
+    kShapeTMarchPipe = 14,  // the same, loads of the next term issued before each term
+    kNumShapes = 15
 };
 void batch_shape(int shape, int* sites_waves, int* wave_groups, int* rhs_per_thread);
+inline bool batch_is_tmarch(int shape) { return shape == kShapeTMarch || shape == kShapeTMarchPipe; }
+// Workgroups of a t-march launch of one task.
+__host__ __device__ inline int batch_tmarch_blocks(int T, int steps, int nw, int nrhs) { return T / steps * nw * nrhs; }
 int batch_rhs_per_item(int shape);
 
 template <typename R> struct BatchHopTask {
@@ -184,6 +189,9 @@ template <typename R> struct BatchHopTask {
     // visits each eighth of the time-slices (nt of them) x-group by x-group,
     // nyt tiles filling one (t, x) plane
     int xgroup, nyt, nt;
+    // t-march shapes: each workgroup walks tm_steps time-slices of one tile
+    // of 256 pairs (tm_nw tiles per slice of tm_slice pairs) for one rhs
+    int tm_steps, tm_nw, tm_slice;
     R ph_re[4], ph_im[4], c_re[2], c_im[2], d_re[2], d_im[2];
 };
 constexpr int kMaxBatchTasks = 8;  // lattices per batch (task tables travel as kernel arguments)

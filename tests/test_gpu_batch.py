@@ -45,6 +45,11 @@ def test_hop_mrhs_matches_oracle(dims, nrhs, shape, prec):
     inp = import_many(lat, psis, prec)
     out = lat.new_spinors(nrhs, prec)
     tol = 1e-13 if prec == tm.F64 else 1e-5
+    if tm.tmhop.SHAPES[shape] in tm.tmhop.TMARCH_SHAPES and (dims[1] * dims[2] * dims[3] // 2) % 256:
+        with pytest.raises(tm.TmhError) as e:
+            tm.hop_apply_mrhs(lat, "eo", out, G, inp, kappa, TWIST, prec, shape)
+        assert e.value.status == tm.tmhop.TMH_ERR_UNSUPPORTED
+        return
     for direction in ("eo", "oe"):
         tm.hop_apply_mrhs(lat, direction, out, G, inp, kappa, TWIST, prec, shape)
         for r in range(nrhs):
@@ -222,3 +227,65 @@ def test_batch_cg_mfma_shape(use_graph):
             x = host(tm.spinor_export(m["lat"], m["x"][r]))
             rr = b - oracle.normal(dims, U, x, kappa, mu, THETA_AP)
             assert np.linalg.norm(rr) / np.linalg.norm(b) <= 1.05e-10, (dims, r)
+
+
+@pytest.mark.parametrize("prec", [tm.F64, tm.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("shape", list(tm.tmhop.TMARCH_SHAPES), ids=["tmarch", "tmarch-pipe"])
+@pytest.mark.parametrize("dims", [(32, 16, 16, 16), (64, 8, 8, 16)], ids=["32x16x16x16", "64x8x8x16"])
+def test_hop_mrhs_tmarch_several_steps(dims, shape, prec):
+    """Lattices big enough for the t-march to walk several time-slices per
+    workgroup with 12 right-hand sides (4 and 2 steps): the register ring
+    carries the time neighbours across steps and range boundaries; against
+    the oracle, and within 1e-14 per site of the one-site-per-lane shape in
+    FP64 (the same sums; the compiler may fuse their multiply-adds
+    differently in the two kernels)."""
+    kappa, nrhs = 0.15, 12
+    U = haar(dims, 581)
+    lat = tm.Lattice(dims)
+    G = tm.gauge_import(lat, U, prec)
+    psis = [gauss(lat.Vh, 590 + r) for r in range(nrhs)]
+    inp = import_many(lat, psis, prec)
+    tol = 1e-13 if prec == tm.F64 else 1e-5
+    for direction in ("eo", "oe"):
+        out = lat.new_spinors(nrhs, prec)
+        tm.hop_apply_mrhs(lat, direction, out, G, inp, kappa, TWIST, prec, shape)
+        base = lat.new_spinors(nrhs, prec)
+        tm.hop_apply_mrhs(lat, direction, base, G, inp, kappa, TWIST, prec, 0)
+        for r in (0, 5, 11):
+            ref = oracle.hop(dims, direction, U, psis[r], kappa, TWIST)
+            got = host(tm.spinor_export(lat, out[r], prec))
+            assert site_rel_err(got, ref) <= tol, (direction, r)
+            if prec == tm.F64:
+                assert site_rel_err(got, host(tm.spinor_export(lat, base[r], prec))) <= 1e-14, (direction, r)
+
+
+@pytest.mark.parametrize("use_graph", [False, True], ids=["eager", "graph"])
+@pytest.mark.parametrize("shape", list(tm.tmhop.TMARCH_SHAPES), ids=["tmarch", "tmarch-pipe"])
+def test_batch_cg_tmarch_shapes(shape, use_graph):
+    """The batched CG on the t-march shapes (fused A^-1 store, twist + norm
+    with one partial per system and slice tile, CG update) over two
+    lattices, one walking two time-slices per workgroup: certified by the
+    oracle and iterating like the single-system CG."""
+    kappa, mu = 0.1632, mu_of(0.1632, 0.0013)
+    members, host_data = [], []
+    for dims, nrhs, seed in (((32, 16, 16, 16), 4, 601), ((8, 8, 8, 8), 3, 611)):
+        lat = tm.Lattice(dims)
+        U = haar(dims, seed)
+        bs = [gauss(lat.Vh, seed + 1 + r) for r in range(nrhs)]
+        members.append(dict(lat=lat, x=lat.new_spinors(nrhs), b=import_many(lat, bs),
+                            gauge=tm.gauge_import(lat, U), kappa=kappa, mu=mu, theta=THETA_AP))
+        host_data.append((dims, U, bs))
+    it, res, ok = tm.batch_cg_solve(members, 1e-10, 2000, shape, use_graph)
+    assert ok and max(res) <= 1e-10
+    k = 0
+    for m, (dims, U, bs) in zip(members, host_data):
+        for r, b in enumerate(bs):
+            x = host(tm.spinor_export(m["lat"], m["x"][r]))
+            rr = b - oracle.normal(dims, U, x, kappa, mu, THETA_AP)
+            assert np.linalg.norm(rr) / np.linalg.norm(b) <= 1.05e-10, (dims, r)
+            if r == 0:
+                x1 = m["lat"].new_spinor()
+                it1, _, ok1 = tm.cg_solve(m["lat"], x1, m["b"][r].contiguous(), m["gauge"], kappa, mu,
+                                          THETA_AP, 1e-10, 2000)
+                assert ok1 and abs(it1 - it[k]) <= 2
+            k += 1
