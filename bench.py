@@ -180,6 +180,23 @@ def _time_us(fn, reps=10, warm=2):
     return a.elapsed_time(b) * 1e3 / reps
 
 
+COPY_BYTES = 805306368  # the streaming copy the counter summaries check against
+
+
+def copy_reference(lat):
+    """Streaming copies of COPY_BYTES (the achievable-bandwidth reference and
+    the known-size kernel of the counter runs); returns GB/s of the last."""
+    import torch
+
+    from paper_1311_4521_amd import tmhop
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        tmhop.stream_copy(lat, dst, src)
+    us = _time_us(lambda: tmhop.stream_copy(lat, dst, src), reps=3, warm=0)
+    return round(2 * COPY_BYTES / (us * 1e-6) / 1e9, 1)
+
+
 def run_batch(args):
     """12 Gaussian right-hand sides on each of 16^3x32, 24^3x48 and 32^3x64
     (Haar links): one batched CG (one launch per operator step for all 36
@@ -207,6 +224,7 @@ def run_batch(args):
         members.append(dict(lat=lat, x=lat.new_spinors(nrhs), b=B, gauge=G, kappa=kappa, mu=mu,
                             theta=theta))
     big = members[0]
+    copy_gbs = copy_reference(big["lat"])
     names = {v: k for k, v in tm.tmhop.SHAPES.items()}
     hop_shape, tuned_us = tm.autotune_mrhs(big["lat"], big["gauge"], nrhs, tm.F64, args.tune_cache)
     log(f"autotuned tile shape {names[hop_shape]}: {tuned_us:.1f} us per 12-RHS hop at 32^3x64")
@@ -295,6 +313,7 @@ def run_batch(args):
                    "hop_tile_shape": names[hop_shape],
                    "batched_cg_ms_by_shape": {names[k]: round(v, 1) for k, v in cg_ms.items()}},
         "sequential_ms": round(1e3 * t_seq, 2),
+        "copy_GBs": copy_gbs,
         "speedup_vs_sequential": round(t_seq / t_batch, 3),
         "iterations": {"batched_max": max(it), "sequential_max": max(seq_it)},
         "max_true_rel_res": max(res),
@@ -336,6 +355,7 @@ def run_adjoint(args):
     G = tm.gauge_import(lat, U)
     tc, tp = tm.spinor_import(lat, chi), tm.spinor_import(lat, psi)
     F = lat.new_gauge(zero=True)
+    copy_gbs = copy_reference(lat)
     force_us = _time_us(lambda: tm.hop_force(lat, "eo", F, G, tc, tp, kappa, theta))
     qforce_us = _time_us(lambda: tm.qtm_force(lat, F, G, tc, tp, kappa, mu, theta))
     Ut = torch.from_numpy(U).cuda().requires_grad_()
@@ -362,6 +382,7 @@ def run_adjoint(args):
                              "GBs_algorithmic": round(fbytes / (force_us * 1e-6) / 1e9, 1),
                              "frac_of_8TBs": round(fbytes / (force_us * 1e-6) / 8e12, 4)},
         "qtm_force_us": round(qforce_us, 1),
+        "copy_GBs": copy_gbs,
         "autograd_forward_backward_ms": round(ag_us / 1e3, 3),
     }
     print(json.dumps(line), flush=True)

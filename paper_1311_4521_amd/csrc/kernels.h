@@ -58,6 +58,11 @@ struct ForceArgs {
     double cx_re[2], cx_im[2];  // X_eff = c_{s/2} X_s
 };
 hipError_t launch_force(const ForceArgs& a, hipStream_t s);
+// The derivatives of two bilinears Re <X_k, H_k Y_k> (k = 0, 1) whose hopping
+// matrices map opposite parities (a.pout = 1 - b.pout), summed per link
+// before the one read-modify-write of the force; gauge, force, g, kind and
+// phases are taken from a.
+hipError_t launch_force2(const ForceArgs& a, const ForceArgs& b, hipStream_t s);
 
 int hop_blocks(const Geo& g);
 // Workgroups of a t-marching hop launch (tm_steps > 0).
