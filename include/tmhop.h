@@ -256,9 +256,11 @@ tmh_status tmh_cg_solve(tmh_lattice* lat, void* x, const void* b, const void* ga
  * keeping the projected time neighbours of its sites in registers (the
  * workgroups of a tile for all right-hand sides run together, sharing its
  * links), 14 with the loads of the next term issued before each term;
- * lattices whose LX*LY*LZ/2 is not a multiple of 256 get
- * TMH_ERR_UNSUPPORTED for these two.  -1 picks the autotuned shape of the
- * handle (tmh_autotune_mrhs) or a default. */
+ * 15 = t-march with 64 site pairs and 4 right-hand sides per workgroup (its
+ * four waves request the links of each step together); lattices whose
+ * LX*LY*LZ/2 is not a multiple of 256 (64 for 15) get TMH_ERR_UNSUPPORTED
+ * for these three.  -1 picks the autotuned shape of the handle
+ * (tmh_autotune_mrhs) or a default. */
 typedef struct {
     tmh_lattice* lat;      /* every member on the same device, distinct handles */
     int nrhs;              /* right-hand sides (>= 1) */

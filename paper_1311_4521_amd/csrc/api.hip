@@ -1053,21 +1053,25 @@ template <typename R> void batch_traversal(tmh::BatchHopTask<R>& t, const tmh_la
     t.nt = l->dims[0] / 8;
 }
 
-// The t-march shapes need whole tiles of 256 pairs per time-slice.
-bool batch_tmarch_ok(const tmh_lattice* l) {
-    return ((int64_t)l->dims[1] * l->dims[2] * l->dims[3] / 2) % 256 == 0;
+// The t-march shapes need whole tiles (256 pairs, or 64 for the shape with
+// four right-hand sides per workgroup) per time-slice.
+bool batch_tmarch_ok(const tmh_lattice* l, int shape) {
+    return ((int64_t)l->dims[1] * l->dims[2] * l->dims[3] / 2) % (256 / tmh::batch_tmarch_rg(shape)) == 0;
 }
 
 // t-march layout of a task: the fewest ranges of time-slices (dividing T)
-// whose workgroups (tiles x ranges x right-hand sides) reach 512, two per CU,
-// so that every workgroup walks as many slices as the grid allows.
-template <typename R> void batch_tmarch_setup(tmh::BatchHopTask<R>& t, const tmh_lattice* l, int nrhs) {
+// whose workgroups (tiles x ranges x right-hand-side groups) reach 512, two
+// per CU, so that every workgroup walks as many slices as the grid allows.
+template <typename R>
+void batch_tmarch_setup(tmh::BatchHopTask<R>& t, const tmh_lattice* l, int nrhs, int shape) {
     const int T = l->dims[0];
+    t.tm_rg = tmh::batch_tmarch_rg(shape);
     t.tm_slice = l->dims[1] * l->dims[2] * l->dims[3] / 2;
-    t.tm_nw = t.tm_slice / 256;
+    t.tm_nw = t.tm_slice / (256 / t.tm_rg);
+    const int64_t groups = (nrhs + t.tm_rg - 1) / t.tm_rg;
     int ranges = T;
     for (int d = 1; d <= T; ++d)
-        if (T % d == 0 && (int64_t)t.tm_nw * nrhs * d >= 512) {
+        if (T % d == 0 && (int64_t)t.tm_nw * groups * d >= 512) {
             ranges = d;
             break;
         }
@@ -1140,7 +1144,7 @@ tmh_status tmh_hop_apply_mrhs(tmh_lattice* l, tmh_dir dir, void* out, const void
     if (overlap(out, sb, in, sb) || overlap(out, sb, gauge, gauge_bytes(l, prec))) return TMH_ERR_ALIAS;
     DeviceGuard guard(l->device);
     if (shape < 0) shape = default_shape(l, nrhs, prec);
-    if (tmh::batch_is_tmarch(shape) && !batch_tmarch_ok(l)) return TMH_ERR_UNSUPPORTED;
+    if (tmh::batch_is_tmarch(shape) && !batch_tmarch_ok(l, shape)) return TMH_ERR_UNSUPPORTED;
     const int pout = dir == TMH_EO ? 0 : 1;
     const int items = hop_items(l->g, nrhs, shape);
     if (prec == TMH_F64) {
@@ -1150,7 +1154,7 @@ tmh_status tmh_hop_apply_mrhs(tmh_lattice* l, tmh_dir dir, void* out, const void
         tab.t[0] = hop_task<double>(l, pout, out, gauge, in, nullptr, nrhs, theta);
         tab.t[0].c_re[0] = tab.t[0].c_re[1] = kappa;
         batch_traversal(tab.t[0], l, shape);
-        if (tmh::batch_is_tmarch(shape)) batch_tmarch_setup(tab.t[0], l, nrhs);
+        if (tmh::batch_is_tmarch(shape)) batch_tmarch_setup(tab.t[0], l, nrhs, shape);
         TMH_TRY_HIP(tmh::launch_batch_hop<double>(tab, items, shape, 0, l->stream));
     } else {
         tmh::BatchHopTable<float> tab;
@@ -1159,7 +1163,7 @@ tmh_status tmh_hop_apply_mrhs(tmh_lattice* l, tmh_dir dir, void* out, const void
         tab.t[0] = hop_task<float>(l, pout, out, gauge, in, nullptr, nrhs, theta);
         tab.t[0].c_re[0] = tab.t[0].c_re[1] = (float)kappa;
         batch_traversal(tab.t[0], l, shape);
-        if (tmh::batch_is_tmarch(shape)) batch_tmarch_setup(tab.t[0], l, nrhs);
+        if (tmh::batch_is_tmarch(shape)) batch_tmarch_setup(tab.t[0], l, nrhs, shape);
         TMH_TRY_HIP(tmh::launch_batch_hop<float>(tab, items, shape, 0, l->stream));
     }
     return TMH_OK;
@@ -1188,7 +1192,7 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* m, int nmem, double rel_to
     if (shape < 0) shape = default_shape(l0, m[0].nrhs, TMH_F64);
     if (tmh::batch_is_tmarch(shape))
         for (int k = 0; k < nmem; ++k)
-            if (!batch_tmarch_ok(m[k].lat)) return TMH_ERR_UNSUPPORTED;
+            if (!batch_tmarch_ok(m[k].lat, shape)) return TMH_ERR_UNSUPPORTED;
     for (int k = 0; k < nmem; ++k) TMH_TRY(mrhs_scratch(m[k].lat, m[k].nrhs));
     // per-system partial slots, scalars, flags
     int64_t pstride = 1;
@@ -1261,7 +1265,7 @@ tmh_status tmh_batch_cg_solve(const tmh_batch_member* m, int nmem, double rel_to
             }
             t.sys0 = s0;
             t.item0 = H[h].ntasks == 0 ? 0 : H[h].t[H[h].ntasks - 1].item0 + hop_items(m[k - 1].lat->g, m[k - 1].nrhs, shape);
-            if (tmh::batch_is_tmarch(shape)) batch_tmarch_setup(t, l, n);
+            if (tmh::batch_is_tmarch(shape)) batch_tmarch_setup(t, l, n, shape);
             H[h].t[H[h].ntasks++] = t;
         }
         tmh::BatchVecTask vt;
@@ -1496,7 +1500,7 @@ tmh_status tmh_autotune_mrhs(tmh_lattice* l, const void* gauge, int nrhs, tmh_pr
         hipEventCreate(&e1) != hipSuccess)
         st = TMH_ERR_HIP;
     for (int sh = 0; sh < tmh::kNumShapes && st == TMH_OK; ++sh) {
-        if (tmh::batch_is_tmarch(sh) && !batch_tmarch_ok(l)) continue;
+        if (tmh::batch_is_tmarch(sh) && !batch_tmarch_ok(l, sh)) continue;
         for (int w = 0; w < 2 && st == TMH_OK; ++w)
             st = tmh_hop_apply_mrhs(l, TMH_EO, out, gauge, in, nrhs, 0.1, theta, prec, sh);
         if (st != TMH_OK) break;

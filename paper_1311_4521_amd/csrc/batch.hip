@@ -25,9 +25,9 @@
 namespace tmh {
 
 void batch_shape(int shape, int* sw, int* ry, int* nr) {
-    static const int SW[kNumShapes] = {4, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 4, 4};
-    static const int RY[kNumShapes] = {1, 2, 4, 4, 12, 1, 2, 2, 4, 2, 3, 1, 8, 1, 1};
-    static const int NR[kNumShapes] = {1, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4, 1, 1, 1};
+    static const int SW[kNumShapes] = {4, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 4, 4, 1};
+    static const int RY[kNumShapes] = {1, 2, 4, 4, 12, 1, 2, 2, 4, 2, 3, 1, 8, 1, 1, 4};
+    static const int NR[kNumShapes] = {1, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4, 1, 1, 1, 1};
     *sw = SW[shape];
     *ry = RY[shape];
     *nr = NR[shape];
@@ -462,7 +462,7 @@ __device__ __forceinline__ bool tmarch_block(const BatchHopTable<R>& tasks, int&
     int j = blockIdx.x / kXcds;
     for (ti = 0; ti < tasks.ntasks; ++ti) {
         const BatchHopTask<R>& T = tasks.t[ti];
-        const int nb = batch_tmarch_blocks(T.g.L[0], T.tm_steps, T.tm_nw, T.nrhs);
+        const int nb = batch_tmarch_blocks(T.g.L[0], T.tm_steps, T.tm_nw, T.nrhs, T.tm_rg);
         const int q = nb / kXcds, m = nb % kXcds;
         const int cnt = q + (x < m ? 1 : 0);
         if (j < cnt) {
@@ -474,17 +474,30 @@ __device__ __forceinline__ bool tmarch_block(const BatchHopTable<R>& tasks, int&
     return false;
 }
 
-template <typename R, int MODE, bool PIPE>
+// RG right-hand sides per workgroup: its 256 threads are RG groups (of
+// 256 / RG pairs) that walk the same pairs for consecutive right-hand sides,
+// so the links of a step are requested by the RG groups at the same time.
+// The t-march link loads keep the default cache policy: the workgroups of a
+// tile for all right-hand sides read each link through L2 (with the
+// non-temporal hint every right-hand side fetched its links again, 1.7x
+// slower at 32^3x64 with 12 right-hand sides).
+constexpr int kTmLinkAux = 0;
+
+template <typename R, int MODE, bool PIPE, int RG>
 __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> tasks) {
     using W = typename Word<R>::T;
+    constexpr int kPairs = 256 / RG;  // pairs of one tile
     int ti, local;
     if (!tmarch_block(tasks, ti, local)) return;
     const BatchHopTask<R>& T = tasks.t[ti];
-    const int rhs = local % T.nrhs, tmp = local / T.nrhs;
+    const int ngr = (T.nrhs + RG - 1) / RG;
+    const int rgi = local % ngr, tmp = local / ngr;
     const int w = tmp % T.tm_nw, range = tmp / T.tm_nw;
-    if (T.flags && T.flags[2 * (T.sys0 + rhs)]) return;
+    // the same for a whole wave (kPairs is a multiple of 64): kept in an SGPR
+    const int rhs = __builtin_amdgcn_readfirstlane(rgi * RG + (int)threadIdx.x / kPairs);
+    if (rhs >= T.nrhs || (T.flags && T.flags[2 * (T.sys0 + rhs)])) return;
     const int slice = T.tm_slice, LT = T.g.L[0], S = T.g.S;
-    const int jp = w * 256 + threadIdx.x;
+    const int jp = w * kPairs + (int)threadIdx.x % kPairs;
     const int hz = T.g.L[3] >> 1;
     const int row = jp / hz, zp = jp - row * hz;
     const int y = row % T.g.L[2], x = row / T.g.L[2];
@@ -540,7 +553,7 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
         {
             // forward time term from memory; its backward projection joins the ring
             TermData<R> d;
-            load_t<R, 0, 0, 0>(d, b, n, i);
+            load_t<R, 0, kTmLinkAux, 0>(d, b, n, i);
             cx<R> hf[2][3], hn[2][3];
             project<R, 0, +1>(hf, d.psi);
             project<R, 0, -1>(hn, d.psi);
@@ -550,7 +563,7 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
             {
                 const typename Word<R>::T* link = b.gin;
 #pragma unroll
-                for (int k = 0; k < 9; ++k) e.u[k / 3][k % 3] = bload<R>(link + (int64_t)k * S, S, n.jn[1]);
+                for (int k = 0; k < 9; ++k) e.u[k / 3][k % 3] = bload<R, kTmLinkAux>(link + (int64_t)k * S, S, n.jn[1]);
             }
             add_term_h<R, 0, -1>(acc, hprev, e.u, (n.wrap >> 1) & 1u, mk<R>(b.ph_re[0], -b.ph_im[0]));
 #pragma unroll
@@ -564,33 +577,33 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
         TMH_SCHED_FENCE();
         if constexpr (PIPE) {
             TermData<R> d0, d1;
-            load_t<R, 2, 0, 0>(d0, b, n, i);
+            load_t<R, 2, kTmLinkAux, 0>(d0, b, n, i);
             TMH_SCHED_FENCE();
-            load_t<R, 3, 0, 0>(d1, b, n, i);
+            load_t<R, 3, kTmLinkAux, 0>(d1, b, n, i);
             TMH_SCHED_FENCE();
             add_t<R, 2>(acc, d0, b, n);
             TMH_SCHED_FENCE();
-            load_t<R, 4, 0, 0>(d0, b, n, i);
+            load_t<R, 4, kTmLinkAux, 0>(d0, b, n, i);
             TMH_SCHED_FENCE();
             add_t<R, 3>(acc, d1, b, n);
             TMH_SCHED_FENCE();
-            load_t<R, 5, 0, 0>(d1, b, n, i);
+            load_t<R, 5, kTmLinkAux, 0>(d1, b, n, i);
             TMH_SCHED_FENCE();
             add_t<R, 4>(acc, d0, b, n);
             TMH_SCHED_FENCE();
-            load_t<R, 6, 0, 0>(d0, b, n, i);
+            load_t<R, 6, kTmLinkAux, 0>(d0, b, n, i);
             TMH_SCHED_FENCE();
             add_t<R, 5>(acc, d1, b, n);
             TMH_SCHED_FENCE();
-            load_t<R, 7, 0, 0>(d1, b, n, i);
+            load_t<R, 7, kTmLinkAux, 0>(d1, b, n, i);
             TMH_SCHED_FENCE();
             add_t<R, 6>(acc, d0, b, n);
             TMH_SCHED_FENCE();
             add_t<R, 7>(acc, d1, b, n);
         } else {
             TermData<R> d;
-#define TMH_TM_TERM(TT)              \
-    load_t<R, TT, 0, 0>(d, b, n, i); \
+#define TMH_TM_TERM(TT)                       \
+    load_t<R, TT, kTmLinkAux, 0>(d, b, n, i); \
     add_t<R, TT>(acc, d, b, n);      \
     TMH_SCHED_FENCE();
             TMH_TM_TERM(2) TMH_TM_TERM(3) TMH_TM_TERM(4) TMH_TM_TERM(5) TMH_TM_TERM(6) TMH_TM_TERM(7)
@@ -628,16 +641,21 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
             }
         }
         if constexpr (MODE >= 2) {
-            // one partial per (system, slice tile), as the tiles of 256 sites
-            // of the other shapes
+            // one partial per (system, slice tile), as the tiles of 64 * SW
+            // sites of the other shapes
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
-            if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = nrm;
-            __syncthreads();
-            if (threadIdx.x == 0)
-                T.partial[(int64_t)(T.sys0 + rhs) * T.pstride + t * T.tm_nw + w] =
-                    wsum[0] + wsum[1] + wsum[2] + wsum[3];
-            __syncthreads();
+            if constexpr (RG == 1) {
+                if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = nrm;
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    T.partial[(int64_t)(T.sys0 + rhs) * T.pstride + t * T.tm_nw + w] =
+                        wsum[0] + wsum[1] + wsum[2] + wsum[3];
+                __syncthreads();
+            } else {
+                static_assert(kPairs == 64, "one wave per right-hand side and tile");
+                if ((threadIdx.x & 63) == 0) T.partial[(int64_t)(T.sys0 + rhs) * T.pstride + t * T.tm_nw + w] = nrm;
+            }
         }
     }
 }
@@ -838,30 +856,33 @@ static int persistent_grid(const void* fn, int threads, int nitems) {
     return grid < kXcds ? kXcds : grid;
 }
 
-template <typename R, bool PIPE>
+template <typename R, bool PIPE, int RG>
 static hipError_t launch_tmarch(const BatchHopTable<R>& tab, int mode, hipStream_t s) {
     // every XCD's list holds ceil(nb / 8) workgroups of each task at most
     int per_xcd = 0;
-    for (int k = 0; k < tab.ntasks; ++k)
-        per_xcd += (batch_tmarch_blocks(tab.t[k].g.L[0], tab.t[k].tm_steps, tab.t[k].tm_nw, tab.t[k].nrhs) +
-                    kXcds - 1) / kXcds;
+    for (int k = 0; k < tab.ntasks; ++k) {
+        const BatchHopTask<R>& t = tab.t[k];
+        if (t.tm_rg != RG) return hipErrorInvalidValue;
+        per_xcd += (batch_tmarch_blocks(t.g.L[0], t.tm_steps, t.tm_nw, t.nrhs, RG) + kXcds - 1) / kXcds;
+    }
     const int grid = per_xcd * kXcds;
     if (grid == 0) return hipSuccess;
     switch (mode) {
-        case 0: hipLaunchKernelGGL((batch_tmarch_kernel<R, 0, PIPE>), dim3(grid), dim3(256), 0, s, tab); break;
-        case 1: hipLaunchKernelGGL((batch_tmarch_kernel<R, 1, PIPE>), dim3(grid), dim3(256), 0, s, tab); break;
-        case 2: hipLaunchKernelGGL((batch_tmarch_kernel<R, 2, PIPE>), dim3(grid), dim3(256), 0, s, tab); break;
-        default: hipLaunchKernelGGL((batch_tmarch_kernel<R, 3, PIPE>), dim3(grid), dim3(256), 0, s, tab); break;
+        case 0: hipLaunchKernelGGL((batch_tmarch_kernel<R, 0, PIPE, RG>), dim3(grid), dim3(256), 0, s, tab); break;
+        case 1: hipLaunchKernelGGL((batch_tmarch_kernel<R, 1, PIPE, RG>), dim3(grid), dim3(256), 0, s, tab); break;
+        case 2: hipLaunchKernelGGL((batch_tmarch_kernel<R, 2, PIPE, RG>), dim3(grid), dim3(256), 0, s, tab); break;
+        default: hipLaunchKernelGGL((batch_tmarch_kernel<R, 3, PIPE, RG>), dim3(grid), dim3(256), 0, s, tab); break;
     }
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_batch_hop(const BatchHopTable<R>& tasks, int nitems, int shape, int mode, hipStream_t s) {
-    // t-march shapes: the host has set tm_steps, tm_nw and tm_slice of every
-    // task (slices of whole tiles of 256 pairs, steps dividing T)
-    if (shape == kShapeTMarch) return launch_tmarch<R, false>(tasks, mode, s);
-    if (shape == kShapeTMarchPipe) return launch_tmarch<R, true>(tasks, mode, s);
+    // t-march shapes: the host has set tm_steps, tm_nw, tm_slice and tm_rg of
+    // every task (slices of whole tiles of 256 / tm_rg pairs, steps dividing T)
+    if (shape == kShapeTMarch) return launch_tmarch<R, false, 1>(tasks, mode, s);
+    if (shape == kShapeTMarchPipe) return launch_tmarch<R, true, 1>(tasks, mode, s);
+    if (shape == kShapeTMarch4) return launch_tmarch<R, false, 4>(tasks, mode, s);
     if (nitems == 0) return hipSuccess;
     int sw, ry, nr;
     batch_shape(shape, &sw, &ry, &nr);

@@ -166,12 +166,20 @@ enum BatchShapeId {
     kShapeMfma = 12,  // 64 sites x 8 right-hand sides, link products on the matrix cores
     kShapeTMarch = 13,      // t-march: a workgroup walks time-slices for one tile and one rhs
     kShapeTMarchPipe = 14,  // the same, loads of the next term issued before each term
-    kNumShapes = 15
+    kShapeTMarch4 = 15,     // t-march: a workgroup walks time-slices for 64 pairs and 4 rhs
+    kNumShapes = 16
 };
 void batch_shape(int shape, int* sites_waves, int* wave_groups, int* rhs_per_thread);
-inline bool batch_is_tmarch(int shape) { return shape == kShapeTMarch || shape == kShapeTMarchPipe; }
+inline bool batch_is_tmarch(int shape) {
+    return shape == kShapeTMarch || shape == kShapeTMarchPipe || shape == kShapeTMarch4;
+}
+// Right-hand sides of one t-march workgroup (its 256 threads are 256 / rg
+// pairs times rg right-hand sides).
+inline int batch_tmarch_rg(int shape) { return shape == kShapeTMarch4 ? 4 : 1; }
 // Workgroups of a t-march launch of one task.
-__host__ __device__ inline int batch_tmarch_blocks(int T, int steps, int nw, int nrhs) { return T / steps * nw * nrhs; }
+__host__ __device__ inline int batch_tmarch_blocks(int T, int steps, int nw, int nrhs, int rg) {
+    return T / steps * nw * ((nrhs + rg - 1) / rg);
+}
 int batch_rhs_per_item(int shape);
 
 template <typename R> struct BatchHopTask {
@@ -195,8 +203,9 @@ template <typename R> struct BatchHopTask {
     // nyt tiles filling one (t, x) plane
     int xgroup, nyt, nt;
     // t-march shapes: each workgroup walks tm_steps time-slices of one tile
-    // of 256 pairs (tm_nw tiles per slice of tm_slice pairs) for one rhs
-    int tm_steps, tm_nw, tm_slice;
+    // of 256 / tm_rg pairs (tm_nw tiles per slice of tm_slice pairs) for
+    // tm_rg right-hand sides
+    int tm_steps, tm_nw, tm_slice, tm_rg;
     R ph_re[4], ph_im[4], c_re[2], c_im[2], d_re[2], d_im[2];
 };
 constexpr int kMaxBatchTasks = 8;  // lattices per batch (task tables travel as kernel arguments)

@@ -31,8 +31,9 @@ def import_many(lat, fields, prec=tm.F64):
 @pytest.mark.parametrize("prec", [tm.F64, tm.F32], ids=["f64", "f32"])
 @pytest.mark.parametrize("shape", list(tm.tmhop.SHAPES))
 @pytest.mark.parametrize("dims,nrhs", [((6, 8, 10, 4), 3), ((8, 8, 8, 8), 12), ((2, 2, 2, 2), 5),
-                                       ((8, 6, 16, 16), 12), ((16, 4, 16, 32), 5)],
-                         ids=["6x8x10x4-3", "8x8x8x8-12", "2x2x2x2-5", "8x6x16x16-12", "16x4x16x32-5"])
+                                       ((8, 6, 16, 16), 12), ((16, 4, 16, 32), 5), ((6, 4, 8, 4), 7)],
+                         ids=["6x8x10x4-3", "8x8x8x8-12", "2x2x2x2-5", "8x6x16x16-12", "16x4x16x32-5",
+                              "6x4x8x4-7"])
 def test_hop_mrhs_matches_oracle(dims, nrhs, shape, prec):
     """The last two lattices take the x-group tile order (whole (t, x)
     planes of 128 and 256 sites, T a multiple of 8) for the shapes whose
@@ -45,7 +46,8 @@ def test_hop_mrhs_matches_oracle(dims, nrhs, shape, prec):
     inp = import_many(lat, psis, prec)
     out = lat.new_spinors(nrhs, prec)
     tol = 1e-13 if prec == tm.F64 else 1e-5
-    if tm.tmhop.SHAPES[shape] in tm.tmhop.TMARCH_SHAPES and (dims[1] * dims[2] * dims[3] // 2) % 256:
+    sid = tm.tmhop.SHAPES[shape]
+    if sid in tm.tmhop.TMARCH_SHAPES and (dims[1] * dims[2] * dims[3] // 2) % (64 if sid == 15 else 256):
         with pytest.raises(tm.TmhError) as e:
             tm.hop_apply_mrhs(lat, "eo", out, G, inp, kappa, TWIST, prec, shape)
         assert e.value.status == tm.tmhop.TMH_ERR_UNSUPPORTED
@@ -230,7 +232,7 @@ def test_batch_cg_mfma_shape(use_graph):
 
 
 @pytest.mark.parametrize("prec", [tm.F64, tm.F32], ids=["f64", "f32"])
-@pytest.mark.parametrize("shape", list(tm.tmhop.TMARCH_SHAPES), ids=["tmarch", "tmarch-pipe"])
+@pytest.mark.parametrize("shape", list(tm.tmhop.TMARCH_SHAPES), ids=["tmarch", "tmarch-pipe", "tmarch4"])
 @pytest.mark.parametrize("dims", [(32, 16, 16, 16), (64, 8, 8, 16)], ids=["32x16x16x16", "64x8x8x16"])
 def test_hop_mrhs_tmarch_several_steps(dims, shape, prec):
     """Lattices big enough for the t-march to walk several time-slices per
@@ -260,7 +262,7 @@ def test_hop_mrhs_tmarch_several_steps(dims, shape, prec):
 
 
 @pytest.mark.parametrize("use_graph", [False, True], ids=["eager", "graph"])
-@pytest.mark.parametrize("shape", list(tm.tmhop.TMARCH_SHAPES), ids=["tmarch", "tmarch-pipe"])
+@pytest.mark.parametrize("shape", list(tm.tmhop.TMARCH_SHAPES), ids=["tmarch", "tmarch-pipe", "tmarch4"])
 def test_batch_cg_tmarch_shapes(shape, use_graph):
     """The batched CG on the t-march shapes (fused A^-1 store, twist + norm
     with one partial per system and slice tile, CG update) over two
