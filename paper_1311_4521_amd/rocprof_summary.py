@@ -112,6 +112,23 @@ def traffic(fetch_dir, write_dir, out_json, copy_bytes=None, sites=None):
     return res
 
 
+def short_name(name: str, width: int = 70) -> str:
+    """Kernel name without the namespace, the return type and the parameter
+    list (the template arguments stay), cut to `width` characters."""
+    n = name[5:] if name.startswith("void ") else name
+    n = n.replace("tmh::(anonymous namespace)::", "").replace("tmh::", "")
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0 and i > 0:
+            n = n[:i]
+            break
+    return n if len(n) <= width else n[: width - 3] + "..."
+
+
 def stats(stats_csv, out_md):
     """Per-kernel table from rocprofv3's kernel statistics.  When the kernel
     trace of the same run sits beside it (``*_kernel_trace.csv``), the table
@@ -137,7 +154,7 @@ def stats(stats_csv, out_md):
              "|---|---|---|---|---|---|---|"]
     for r in rows[:24]:
         name = r["Name"]
-        short = name if len(name) <= 70 else name[:67] + "..."
+        short = short_name(name)
         ex, avg = work.get(name, (None, None))
         lines.append(f"| `{short}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} | "
@@ -184,7 +201,7 @@ def requests(read_dir, write_dir, out_md, sites, copy_bytes, command=""):
              "| kernel | launches | read MB | write MB | read B/site | write B/site | DRAM read requests |",
              "|---|---|---|---|---|---|---|"]
     for k, (r, w, n, d) in sorted(res.items(), key=lambda kv: -kv[1][0]):
-        short = k if len(k) <= 90 else k[:87] + "..."
+        short = short_name(k, 90)
         lines.append(f"| `{short}` | {n} | {r / 1e6:.1f} | {w / 1e6:.1f} | {r / sites:.1f} | {w / sites:.1f} | "
                      f"{'' if d is None else f'{d:,.0f}'} |")
     with open(out_md, "w") as fh:
