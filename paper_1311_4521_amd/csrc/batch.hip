@@ -25,9 +25,9 @@
 namespace tmh {
 
 void batch_shape(int shape, int* sw, int* ry, int* nr) {
-    static const int SW[kNumShapes] = {4, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 4, 4, 1};
-    static const int RY[kNumShapes] = {1, 2, 4, 4, 12, 1, 2, 2, 4, 2, 3, 1, 8, 1, 1, 4};
-    static const int NR[kNumShapes] = {1, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4, 1, 1, 1, 1};
+    static const int SW[kNumShapes] = {4, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 2, 1, 4, 4, 1, 1};
+    static const int RY[kNumShapes] = {1, 2, 4, 4, 12, 1, 2, 2, 4, 2, 3, 1, 8, 1, 1, 4, 4};
+    static const int NR[kNumShapes] = {1, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4, 1, 1, 1, 1, 1};
     *sw = SW[shape];
     *ry = RY[shape];
     *nr = NR[shape];
@@ -482,11 +482,50 @@ __device__ __forceinline__ bool tmarch_block(const BatchHopTable<R>& tasks, int&
 // non-temporal hint every right-hand side fetched its links again, 1.7x
 // slower at 32^3x64 with 12 right-hand sides).
 constexpr int kTmLinkAux = 0;
+// Staged links are loaded once per workgroup and step.
+#ifndef TMH_TM_STAGE_NT
+#define TMH_TM_STAGE_NT 0
+#endif
+constexpr int kTmStageAux = TMH_TM_STAGE_NT ? TMH_LINK_POLICY : 0;
 
-template <typename R, int MODE, bool PIPE, int RG>
+// Links of term TT of one step for the tile's pair `lane`, into LDS at
+// [TT][entry][lane] (each of the workgroup's right-hand sides reads them
+// there).
+template <typename R, int TT>
+__device__ __forceinline__ void tm_stage(cx<R>* lk, const HopArgs<R>& b, const SiteNb& n, int i, int lane) {
+    constexpr int MU = TT / 2;
+    const int S = b.g.S;
+    const typename Word<R>::T* link = (TT % 2 == 0 ? b.gout : b.gin) + (int64_t)MU * 9 * S;
+    const int jl = TT % 2 == 0 ? i : n.jn[TT];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) lk[(TT * 9 + k) * 64 + lane] = bload<R, kTmStageAux>(link + (int64_t)k * S, S, jl);
+}
+
+// The neighbour spinor of term TT from memory and its link from memory or
+// from the staged links.
+template <typename R, int TT, bool LDS>
+__device__ __forceinline__ void tm_load(TermData<R>& d, const HopArgs<R>& b, const SiteNb& n, int i, const cx<R>* lk) {
+    if constexpr (LDS) {
+        const int S = b.g.S;
+        const int lane = (int)threadIdx.x % 64;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) d.psi[s][a] = bload<R>(b.in + (int64_t)(3 * s + a) * S, S, n.jn[TT]);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) d.u[k / 3][k % 3] = lk[(TT * 9 + k) * 64 + lane];
+    } else {
+        load_t<R, TT, kTmLinkAux, 0>(d, b, n, i);
+    }
+}
+
+template <typename R, int MODE, bool PIPE, int RG, bool LDS>
 __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> tasks) {
     using W = typename Word<R>::T;
     constexpr int kPairs = 256 / RG;  // pairs of one tile
+    static_assert(!LDS || (RG == 4 && !PIPE), "links are staged for one wave per right-hand side");
+    extern __shared__ unsigned char tm_lds[];
+    cx<R>* lk = reinterpret_cast<cx<R>*>(tm_lds);  // LDS: [term][entry][pair] links of one step
     int ti, local;
     if (!tmarch_block(tasks, ti, local)) return;
     const BatchHopTask<R>& T = tasks.t[ti];
@@ -494,15 +533,29 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
     const int rgi = local % ngr, tmp = local / ngr;
     const int w = tmp % T.tm_nw, range = tmp / T.tm_nw;
     // the same for a whole wave (kPairs is a multiple of 64): kept in an SGPR
-    const int rhs = __builtin_amdgcn_readfirstlane(rgi * RG + (int)threadIdx.x / kPairs);
-    if (rhs >= T.nrhs || (T.flags && T.flags[2 * (T.sys0 + rhs)])) return;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kPairs);
+    const int rhs = rgi * RG + wave;
+    const bool active = rhs < T.nrhs && !(T.flags && T.flags[2 * (T.sys0 + rhs)]);
+    if constexpr (!LDS) {
+        if (!active) return;
+    } else {
+        // the waves stage the links together: the workgroup stays while one
+        // of its right-hand sides is still iterating
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+            const int q = rgi * RG + r;
+            any = any || (q < T.nrhs && !(T.flags && T.flags[2 * (T.sys0 + q)]));
+        }
+        if (!any) return;
+    }
     const int slice = T.tm_slice, LT = T.g.L[0], S = T.g.S;
     const int jp = w * kPairs + (int)threadIdx.x % kPairs;
     const int hz = T.g.L[3] >> 1;
     const int row = jp / hz, zp = jp - row * hz;
     const int y = row % T.g.L[2], x = row / T.g.L[2];
     const int t0 = range * T.tm_steps;
-    const int64_t fo = (int64_t)rhs * T.fstride;
+    const int64_t fo = (int64_t)(active ? rhs : rgi * RG) * T.fstride;
     HopArgs<R> a;
     a.in = T.in + fo;
     a.gout = T.gout;
@@ -516,7 +569,7 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
         a.ph_im[m] = T.ph_im[m];
     }
     cx<R> hprev[2][3], hcur[2][3];
-    {
+    if (active) {
         cx<R> psi[4][3];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
@@ -530,7 +583,7 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
             for (int c = 0; c < 3; ++c) psi[s][c] = bload<R>(a.in + (int64_t)(3 * s + c) * S, S, t0 * slice + jp);
         project<R, 0, -1>(hcur, psi);
     }
-    const R alpha = MODE == 3 ? (R)T.scal[(int64_t)(T.sys0 + rhs) * kNScal + kAlpha] : (R)0;
+    const R alpha = (MODE == 3 && active) ? (R)T.scal[(int64_t)(T.sys0 + rhs) * kNScal + kAlpha] : (R)0;
     __shared__ double wsum[4];
     for (int st = 0; st < T.tm_steps; ++st) {
         HopArgs<R> b = a;
@@ -545,6 +598,18 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
         c[3] = 2 * zp + ((t + x + y + T.pout) & 1);
         const int lex = ((t * T.g.L[1] + x) * T.g.L[2] + y) * T.g.L[3] + c[3];
         const SiteNb n = site_neighbours(T.g, c, lex);
+        if constexpr (LDS) {
+            // wave v loads the links of terms 2v and 2v + 1 of the tile's pairs
+            const int lane = (int)threadIdx.x % kPairs;
+            switch (wave) {
+                case 0: tm_stage<R, 0>(lk, b, n, i, lane); tm_stage<R, 1>(lk, b, n, i, lane); break;
+                case 1: tm_stage<R, 2>(lk, b, n, i, lane); tm_stage<R, 3>(lk, b, n, i, lane); break;
+                case 2: tm_stage<R, 4>(lk, b, n, i, lane); tm_stage<R, 5>(lk, b, n, i, lane); break;
+                default: tm_stage<R, 6>(lk, b, n, i, lane); tm_stage<R, 7>(lk, b, n, i, lane); break;
+            }
+            __syncthreads();
+        }
+        if (active) {
         cx<R> acc[4][3];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
@@ -553,14 +618,18 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
         {
             // forward time term from memory; its backward projection joins the ring
             TermData<R> d;
-            load_t<R, 0, kTmLinkAux, 0>(d, b, n, i);
+            tm_load<R, 0, LDS>(d, b, n, i, lk);
             cx<R> hf[2][3], hn[2][3];
             project<R, 0, +1>(hf, d.psi);
             project<R, 0, -1>(hn, d.psi);
             add_term_h<R, 0, +1>(acc, hf, d.u, (n.wrap >> 0) & 1u, mk<R>(b.ph_re[0], b.ph_im[0]));
             // backward time term from the ring
             TermData<R> e;
-            {
+            if constexpr (LDS) {
+                const int lane = (int)threadIdx.x % kPairs;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) e.u[k / 3][k % 3] = lk[(9 + k) * 64 + lane];
+            } else {
                 const typename Word<R>::T* link = b.gin;
 #pragma unroll
                 for (int k = 0; k < 9; ++k) e.u[k / 3][k % 3] = bload<R, kTmLinkAux>(link + (int64_t)k * S, S, n.jn[1]);
@@ -602,9 +671,9 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
             add_t<R, 7>(acc, d1, b, n);
         } else {
             TermData<R> d;
-#define TMH_TM_TERM(TT)                       \
-    load_t<R, TT, kTmLinkAux, 0>(d, b, n, i); \
-    add_t<R, TT>(acc, d, b, n);      \
+#define TMH_TM_TERM(TT)                \
+    tm_load<R, TT, LDS>(d, b, n, i, lk); \
+    add_t<R, TT>(acc, d, b, n);          \
     TMH_SCHED_FENCE();
             TMH_TM_TERM(2) TMH_TM_TERM(3) TMH_TM_TERM(4) TMH_TM_TERM(5) TMH_TM_TERM(6) TMH_TM_TERM(7)
 #undef TMH_TM_TERM
@@ -657,6 +726,8 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
                 if ((threadIdx.x & 63) == 0) T.partial[(int64_t)(T.sys0 + rhs) * T.pstride + t * T.tm_nw + w] = nrm;
             }
         }
+        }  // active
+        if constexpr (LDS) __syncthreads();  // the next step overwrites the staged links
     }
 }
 
@@ -856,7 +927,7 @@ static int persistent_grid(const void* fn, int threads, int nitems) {
     return grid < kXcds ? kXcds : grid;
 }
 
-template <typename R, bool PIPE, int RG>
+template <typename R, bool PIPE, int RG, bool LDS>
 static hipError_t launch_tmarch(const BatchHopTable<R>& tab, int mode, hipStream_t s) {
     // every XCD's list holds ceil(nb / 8) workgroups of each task at most
     int per_xcd = 0;
@@ -867,11 +938,29 @@ static hipError_t launch_tmarch(const BatchHopTable<R>& tab, int mode, hipStream
     }
     const int grid = per_xcd * kXcds;
     if (grid == 0) return hipSuccess;
+    const unsigned lds = LDS ? 8 * 9 * 64 * sizeof(cx<R>) : 0;
+    if (lds > 65536) {
+        // above the default limit of dynamic LDS per workgroup (gfx950 has
+        // 160 KB per CU)
+        static bool raised[4] = {false, false, false, false};
+        if (!raised[mode & 3]) {
+            const void* fn = nullptr;
+            switch (mode) {
+                case 0: fn = reinterpret_cast<const void*>(&batch_tmarch_kernel<R, 0, PIPE, RG, LDS>); break;
+                case 1: fn = reinterpret_cast<const void*>(&batch_tmarch_kernel<R, 1, PIPE, RG, LDS>); break;
+                case 2: fn = reinterpret_cast<const void*>(&batch_tmarch_kernel<R, 2, PIPE, RG, LDS>); break;
+                default: fn = reinterpret_cast<const void*>(&batch_tmarch_kernel<R, 3, PIPE, RG, LDS>); break;
+            }
+            const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            raised[mode & 3] = true;
+        }
+    }
     switch (mode) {
-        case 0: hipLaunchKernelGGL((batch_tmarch_kernel<R, 0, PIPE, RG>), dim3(grid), dim3(256), 0, s, tab); break;
-        case 1: hipLaunchKernelGGL((batch_tmarch_kernel<R, 1, PIPE, RG>), dim3(grid), dim3(256), 0, s, tab); break;
-        case 2: hipLaunchKernelGGL((batch_tmarch_kernel<R, 2, PIPE, RG>), dim3(grid), dim3(256), 0, s, tab); break;
-        default: hipLaunchKernelGGL((batch_tmarch_kernel<R, 3, PIPE, RG>), dim3(grid), dim3(256), 0, s, tab); break;
+        case 0: hipLaunchKernelGGL((batch_tmarch_kernel<R, 0, PIPE, RG, LDS>), dim3(grid), dim3(256), lds, s, tab); break;
+        case 1: hipLaunchKernelGGL((batch_tmarch_kernel<R, 1, PIPE, RG, LDS>), dim3(grid), dim3(256), lds, s, tab); break;
+        case 2: hipLaunchKernelGGL((batch_tmarch_kernel<R, 2, PIPE, RG, LDS>), dim3(grid), dim3(256), lds, s, tab); break;
+        default: hipLaunchKernelGGL((batch_tmarch_kernel<R, 3, PIPE, RG, LDS>), dim3(grid), dim3(256), lds, s, tab); break;
     }
     return hipGetLastError();
 }
@@ -880,9 +969,10 @@ template <typename R>
 hipError_t launch_batch_hop(const BatchHopTable<R>& tasks, int nitems, int shape, int mode, hipStream_t s) {
     // t-march shapes: the host has set tm_steps, tm_nw, tm_slice and tm_rg of
     // every task (slices of whole tiles of 256 / tm_rg pairs, steps dividing T)
-    if (shape == kShapeTMarch) return launch_tmarch<R, false, 1>(tasks, mode, s);
-    if (shape == kShapeTMarchPipe) return launch_tmarch<R, true, 1>(tasks, mode, s);
-    if (shape == kShapeTMarch4) return launch_tmarch<R, false, 4>(tasks, mode, s);
+    if (shape == kShapeTMarch) return launch_tmarch<R, false, 1, false>(tasks, mode, s);
+    if (shape == kShapeTMarchPipe) return launch_tmarch<R, true, 1, false>(tasks, mode, s);
+    if (shape == kShapeTMarch4) return launch_tmarch<R, false, 4, false>(tasks, mode, s);
+    if (shape == kShapeTMarchLds) return launch_tmarch<R, false, 4, true>(tasks, mode, s);
     if (nitems == 0) return hipSuccess;
     int sw, ry, nr;
     batch_shape(shape, &sw, &ry, &nr);

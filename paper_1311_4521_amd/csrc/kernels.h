@@ -167,15 +167,16 @@ enum BatchShapeId {
     kShapeTMarch = 13,      // t-march: a workgroup walks time-slices for one tile and one rhs
     kShapeTMarchPipe = 14,  // the same, loads of the next term issued before each term
     kShapeTMarch4 = 15,     // t-march: a workgroup walks time-slices for 64 pairs and 4 rhs
-    kNumShapes = 16
+    kShapeTMarchLds = 16,   // the same, each step's links staged once in LDS for the 4 rhs
+    kNumShapes = 17
 };
 void batch_shape(int shape, int* sites_waves, int* wave_groups, int* rhs_per_thread);
 inline bool batch_is_tmarch(int shape) {
-    return shape == kShapeTMarch || shape == kShapeTMarchPipe || shape == kShapeTMarch4;
+    return shape == kShapeTMarch || shape == kShapeTMarchPipe || shape == kShapeTMarch4 || shape == kShapeTMarchLds;
 }
 // Right-hand sides of one t-march workgroup (its 256 threads are 256 / rg
 // pairs times rg right-hand sides).
-inline int batch_tmarch_rg(int shape) { return shape == kShapeTMarch4 ? 4 : 1; }
+inline int batch_tmarch_rg(int shape) { return (shape == kShapeTMarch4 || shape == kShapeTMarchLds) ? 4 : 1; }
 // Workgroups of a t-march launch of one task.
 __host__ __device__ inline int batch_tmarch_blocks(int T, int steps, int nw, int nrhs, int rg) {
     return T / steps * nw * ((nrhs + rg - 1) / rg);

@@ -373,9 +373,9 @@ def solve_full(lat: Lattice, x_even, x_odd, b_even, b_odd, gauge, kappa, mu, the
 # products run on the matrix cores
 SHAPES = {"256x1": 0, "128x2": 1, "64x4": 2, "128x4": 3, "64x12": 4, "128x2/r2": 5, "64x4/r2": 6,
           "128x4/r2": 7, "64x12/r3": 8, "128x6/r3": 9, "64x12/r4": 10, "128x4/r4": 11, "64x8/mfma": 12,
-          "256x1/tmarch": 13, "256x1/tmarch-pipe": 14, "64x4/tmarch": 15}
+          "256x1/tmarch": 13, "256x1/tmarch-pipe": 14, "64x4/tmarch": 15, "64x4/tmarch-lds": 16}
 MFMA = 12
-TMARCH_SHAPES = (13, 14, 15)
+TMARCH_SHAPES = (13, 14, 15, 16)
 
 
 def _expect_multi(t, lat, prec, nrhs):

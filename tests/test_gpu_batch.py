@@ -47,7 +47,7 @@ def test_hop_mrhs_matches_oracle(dims, nrhs, shape, prec):
     out = lat.new_spinors(nrhs, prec)
     tol = 1e-13 if prec == tm.F64 else 1e-5
     sid = tm.tmhop.SHAPES[shape]
-    if sid in tm.tmhop.TMARCH_SHAPES and (dims[1] * dims[2] * dims[3] // 2) % (64 if sid == 15 else 256):
+    if sid in tm.tmhop.TMARCH_SHAPES and (dims[1] * dims[2] * dims[3] // 2) % (64 if sid in (15, 16) else 256):
         with pytest.raises(tm.TmhError) as e:
             tm.hop_apply_mrhs(lat, "eo", out, G, inp, kappa, TWIST, prec, shape)
         assert e.value.status == tm.tmhop.TMH_ERR_UNSUPPORTED
@@ -232,7 +232,7 @@ def test_batch_cg_mfma_shape(use_graph):
 
 
 @pytest.mark.parametrize("prec", [tm.F64, tm.F32], ids=["f64", "f32"])
-@pytest.mark.parametrize("shape", list(tm.tmhop.TMARCH_SHAPES), ids=["tmarch", "tmarch-pipe", "tmarch4"])
+@pytest.mark.parametrize("shape", list(tm.tmhop.TMARCH_SHAPES), ids=["tmarch", "tmarch-pipe", "tmarch4", "tmarch4-lds"])
 @pytest.mark.parametrize("dims", [(32, 16, 16, 16), (64, 8, 8, 16)], ids=["32x16x16x16", "64x8x8x16"])
 def test_hop_mrhs_tmarch_several_steps(dims, shape, prec):
     """Lattices big enough for the t-march to walk several time-slices per
@@ -262,7 +262,7 @@ def test_hop_mrhs_tmarch_several_steps(dims, shape, prec):
 
 
 @pytest.mark.parametrize("use_graph", [False, True], ids=["eager", "graph"])
-@pytest.mark.parametrize("shape", list(tm.tmhop.TMARCH_SHAPES), ids=["tmarch", "tmarch-pipe", "tmarch4"])
+@pytest.mark.parametrize("shape", list(tm.tmhop.TMARCH_SHAPES), ids=["tmarch", "tmarch-pipe", "tmarch4", "tmarch4-lds"])
 def test_batch_cg_tmarch_shapes(shape, use_graph):
     """The batched CG on the t-march shapes (fused A^-1 store, twist + norm
     with one partial per system and slice tile, CG update) over two
