@@ -349,8 +349,9 @@ tmh_status tmh_hop_force(tmh_lattice* lat, tmh_dir dir, void* force, const void*
                          const double theta[4], double coeff, tmh_force_kind kind);
 
 /* The same for L = Re <chi, Qhat(sign) psi> (chi, psi odd, FP64): two
- * hopping-matrix launches into the handle's even scratch and two force
- * launches.  For L = |Qhat psi|^2 pass chi = 2 Qhat psi.  The psi-gradient
+ * hopping-matrix launches into the handle's even scratch and one force
+ * launch that adds the terms of both bilinears (through H_oe and H_eo) of
+ * each link in one read-modify-write.  For L = |Qhat psi|^2 pass chi = 2 Qhat psi.  The psi-gradient
  * of L is Qhat(-sign) chi (tmh_qtm_apply). */
 tmh_status tmh_qtm_force(tmh_lattice* lat, void* force, const void* gauge, const void* chi,
                          const void* psi, double kappa, double mu, const double theta[4],

@@ -112,3 +112,14 @@ def test_gaps_share_between_kernels(tmp_path):
             w.writerow({"Kernel_Name": name, "Start_Timestamp": s, "End_Timestamp": e})
     assert rs.gaps(str(p), "batch_") == (330, 450, 4)
     assert rs.gaps(str(p), "batch_", 2) == (140, 150, 2)
+
+
+def test_short_name_keeps_template_arguments():
+    assert rs.short_name("void tmh::(anonymous namespace)::batch_tmarch_kernel<double, 0, false, 4, true>"
+                         "(tmh::BatchHopTable<double>)") == "batch_tmarch_kernel<double, 0, false, 4, true>"
+    assert rs.short_name("tmh::(anonymous namespace)::stream_copy_kernel(unsigned int __vector(4)*, long)") == \
+        "stream_copy_kernel"
+    assert rs.short_name("void tmh::hop_kernel<tmh::half_t, 0, 1>(tmh::HopArgs<tmh::half_t>)") == \
+        "hop_kernel<half_t, 0, 1>"
+    long = "void at::native::elementwise_kernel<" + "x" * 100 + ">(int)"
+    assert rs.short_name(long, 40).endswith("...") and len(rs.short_name(long, 40)) == 40
