@@ -482,11 +482,9 @@ __device__ __forceinline__ bool tmarch_block(const BatchHopTable<R>& tasks, int&
 // non-temporal hint every right-hand side fetched its links again, 1.7x
 // slower at 32^3x64 with 12 right-hand sides).
 constexpr int kTmLinkAux = 0;
-// Staged links are loaded once per workgroup and step.
-#ifndef TMH_TM_STAGE_NT
-#define TMH_TM_STAGE_NT 0
-#endif
-constexpr int kTmStageAux = TMH_TM_STAGE_NT ? TMH_LINK_POLICY : 0;
+// Staged links keep the default policy too: the workgroups of a tile for the
+// other right-hand-side groups load the same links at about the same time.
+constexpr int kTmStageAux = 0;
 
 // Links of term TT of one step for the tile's pair `lane`, into LDS at
 // [TT][entry][lane] (each of the workgroup's right-hand sides reads them
