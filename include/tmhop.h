@@ -258,8 +258,9 @@ tmh_status tmh_cg_solve(tmh_lattice* lat, void* x, const void* b, const void* ga
  * links), 14 with the loads of the next term issued before each term;
  * 15 = t-march with 64 site pairs and 4 right-hand sides per workgroup (its
  * four waves request the links of each step together), 16 the same with
- * each step's links loaded once into LDS (72 KB per workgroup in FP64) and
- * read there by the four right-hand sides; lattices whose LX*LY*LZ/2 is not
+ * each step's links loaded once into LDS (72 KB per workgroup in FP64, half
+ * of them fetched while the other half is used) and read there by the four
+ * right-hand sides; lattices whose LX*LY*LZ/2 is not
  * a multiple of 256 (64 for 15 and 16) get TMH_ERR_UNSUPPORTED for these
  * four.  -1 picks the autotuned shape of the handle
  * (tmh_autotune_mrhs) or a default. */

@@ -486,17 +486,33 @@ constexpr int kTmLinkAux = 0;
 // other right-hand-side groups load the same links at about the same time.
 constexpr int kTmStageAux = 0;
 
-// Links of term TT of one step for the tile's pair `lane`, into LDS at
-// [TT][entry][lane] (each of the workgroup's right-hand sides reads them
-// there).
+// The link of term TT of one step for this thread's pair, into registers.
 template <typename R, int TT>
-__device__ __forceinline__ void tm_stage(cx<R>* lk, const HopArgs<R>& b, const SiteNb& n, int i, int lane) {
+__device__ __forceinline__ void tm_fetch(cx<R> (&u)[9], const HopArgs<R>& b, const SiteNb& n, int i) {
     constexpr int MU = TT / 2;
     const int S = b.g.S;
     const typename Word<R>::T* link = (TT % 2 == 0 ? b.gout : b.gin) + (int64_t)MU * 9 * S;
     const int jl = TT % 2 == 0 ? i : n.jn[TT];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) lk[(TT * 9 + k) * 64 + lane] = bload<R, kTmStageAux>(link + (int64_t)k * S, S, jl);
+    for (int k = 0; k < 9; ++k) u[k] = bload<R, kTmStageAux>(link + (int64_t)k * S, S, jl);
+}
+
+// Wave v's share of one half of a step's links: term 4 * HALF + v.
+template <typename R, int HALF>
+__device__ __forceinline__ void tm_fetch_wave(cx<R> (&u)[9], int wave, const HopArgs<R>& b, const SiteNb& n,
+                                              int i) {
+    switch (wave) {
+        case 0: tm_fetch<R, 4 * HALF + 0>(u, b, n, i); break;
+        case 1: tm_fetch<R, 4 * HALF + 1>(u, b, n, i); break;
+        case 2: tm_fetch<R, 4 * HALF + 2>(u, b, n, i); break;
+        default: tm_fetch<R, 4 * HALF + 3>(u, b, n, i); break;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void tm_put(cx<R>* lk, int term, const cx<R> (&u)[9], int lane) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) lk[(term * 9 + k) * 64 + lane] = u[k];
 }
 
 // The neighbour spinor of term TT from memory and its link from memory or
@@ -518,7 +534,7 @@ __device__ __forceinline__ void tm_load(TermData<R>& d, const HopArgs<R>& b, con
 }
 
 template <typename R, int MODE, bool PIPE, int RG, bool LDS>
-__global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> tasks) {
+__device__ __forceinline__ void tmarch_body(const BatchHopTable<R>& tasks) {
     using W = typename Word<R>::T;
     constexpr int kPairs = 256 / RG;  // pairs of one tile
     static_assert(!LDS || (RG == 4 && !PIPE), "links are staged for one wave per right-hand side");
@@ -583,6 +599,25 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
     }
     const R alpha = (MODE == 3 && active) ? (R)T.scal[(int64_t)(T.sys0 + rhs) * kNScal + kAlpha] : (R)0;
     __shared__ double wsum[4];
+    // LDS: each half of a step's links (terms 0-3, 4-7; wave v holds term
+    // 4 h + v) is fetched into registers while the other half is computed,
+    // then written to LDS; a barrier after each half.
+    const int lane = (int)threadIdx.x % kPairs;
+    cx<R> lreg[9];
+    auto step_nb = [&](int t) {
+        int cc[4];
+        cc[0] = t;
+        cc[1] = x;
+        cc[2] = y;
+        cc[3] = 2 * zp + ((t + x + y + T.pout) & 1);
+        const int lx = ((t * T.g.L[1] + x) * T.g.L[2] + y) * T.g.L[3] + cc[3];
+        return site_neighbours(T.g, cc, lx);
+    };
+    if constexpr (LDS) {
+        tm_fetch_wave<R, 0>(lreg, wave, a, step_nb(t0), t0 * slice + jp);
+        tm_put(lk, wave, lreg, lane);
+        __syncthreads();
+    }
     for (int st = 0; st < T.tm_steps; ++st) {
         HopArgs<R> b = a;
         // rebuilt descriptors every step (see hop_tmarch_kernel)
@@ -596,19 +631,10 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
         c[3] = 2 * zp + ((t + x + y + T.pout) & 1);
         const int lex = ((t * T.g.L[1] + x) * T.g.L[2] + y) * T.g.L[3] + c[3];
         const SiteNb n = site_neighbours(T.g, c, lex);
-        if constexpr (LDS) {
-            // wave v loads the links of terms 2v and 2v + 1 of the tile's pairs
-            const int lane = (int)threadIdx.x % kPairs;
-            switch (wave) {
-                case 0: tm_stage<R, 0>(lk, b, n, i, lane); tm_stage<R, 1>(lk, b, n, i, lane); break;
-                case 1: tm_stage<R, 2>(lk, b, n, i, lane); tm_stage<R, 3>(lk, b, n, i, lane); break;
-                case 2: tm_stage<R, 4>(lk, b, n, i, lane); tm_stage<R, 5>(lk, b, n, i, lane); break;
-                default: tm_stage<R, 6>(lk, b, n, i, lane); tm_stage<R, 7>(lk, b, n, i, lane); break;
-            }
-            __syncthreads();
-        }
-        if (active) {
+        // half B of this step's links, fetched while half A is computed
+        if constexpr (LDS) tm_fetch_wave<R, 1>(lreg, wave, b, n, i);
         cx<R> acc[4][3];
+        if (active) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -624,7 +650,6 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
             // backward time term from the ring
             TermData<R> e;
             if constexpr (LDS) {
-                const int lane = (int)threadIdx.x % kPairs;
 #pragma unroll
                 for (int k = 0; k < 9; ++k) e.u[k / 3][k % 3] = lk[(9 + k) * 64 + lane];
             } else {
@@ -673,9 +698,22 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
     tm_load<R, TT, LDS>(d, b, n, i, lk); \
     add_t<R, TT>(acc, d, b, n);          \
     TMH_SCHED_FENCE();
-            TMH_TM_TERM(2) TMH_TM_TERM(3) TMH_TM_TERM(4) TMH_TM_TERM(5) TMH_TM_TERM(6) TMH_TM_TERM(7)
-#undef TMH_TM_TERM
+            TMH_TM_TERM(2) TMH_TM_TERM(3)
         }
+        }  // active
+        if constexpr (LDS) {
+            // half B in place; after the barrier every wave is also done with
+            // half A, which takes the next step's links
+            tm_put(lk, 4 + wave, lreg, lane);
+            __syncthreads();
+            if (st + 1 < T.tm_steps) tm_fetch_wave<R, 0>(lreg, wave, b, step_nb(t + 1), (t + 1) * slice + jp);
+        }
+        if (active) {
+        if constexpr (!PIPE) {
+            TermData<R> d;
+            TMH_TM_TERM(4) TMH_TM_TERM(5) TMH_TM_TERM(6) TMH_TM_TERM(7)
+        }
+#undef TMH_TM_TERM
         W* out = T.out + fo;
         const W* aux = T.aux + fo;
         W* rio = T.rio + fo;
@@ -725,8 +763,24 @@ __global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> task
             }
         }
         }  // active
-        if constexpr (LDS) __syncthreads();  // the next step overwrites the staged links
+        if constexpr (LDS) {
+            if (st + 1 < T.tm_steps) tm_put(lk, wave, lreg, lane);
+            __syncthreads();  // half A of the next step in place, half B read
+        }
     }
+}
+
+template <typename R, int MODE, bool PIPE, int RG, bool LDS>
+__global__ void __launch_bounds__(256) batch_tmarch_kernel(BatchHopTable<R> tasks) {
+    tmarch_body<R, MODE, PIPE, RG, LDS>(tasks);
+}
+
+// The LDS-staged form with registers held for two waves per SIMD (its
+// twist epilogues would otherwise take a few AGPRs past 256 and drop to one).
+template <typename R, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+batch_tmarch_lds_kernel(BatchHopTable<R> tasks) {
+    tmarch_body<R, MODE, false, 4, true>(tasks);
 }
 
 // ---------------------------------------------------------------- BLAS-1
@@ -944,21 +998,30 @@ static hipError_t launch_tmarch(const BatchHopTable<R>& tab, int mode, hipStream
         if (!raised[mode & 3]) {
             const void* fn = nullptr;
             switch (mode) {
-                case 0: fn = reinterpret_cast<const void*>(&batch_tmarch_kernel<R, 0, PIPE, RG, LDS>); break;
-                case 1: fn = reinterpret_cast<const void*>(&batch_tmarch_kernel<R, 1, PIPE, RG, LDS>); break;
-                case 2: fn = reinterpret_cast<const void*>(&batch_tmarch_kernel<R, 2, PIPE, RG, LDS>); break;
-                default: fn = reinterpret_cast<const void*>(&batch_tmarch_kernel<R, 3, PIPE, RG, LDS>); break;
+                case 0: fn = reinterpret_cast<const void*>(&batch_tmarch_lds_kernel<R, 0>); break;
+                case 1: fn = reinterpret_cast<const void*>(&batch_tmarch_lds_kernel<R, 1>); break;
+                case 2: fn = reinterpret_cast<const void*>(&batch_tmarch_lds_kernel<R, 2>); break;
+                default: fn = reinterpret_cast<const void*>(&batch_tmarch_lds_kernel<R, 3>); break;
             }
             const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             raised[mode & 3] = true;
         }
     }
-    switch (mode) {
-        case 0: hipLaunchKernelGGL((batch_tmarch_kernel<R, 0, PIPE, RG, LDS>), dim3(grid), dim3(256), lds, s, tab); break;
-        case 1: hipLaunchKernelGGL((batch_tmarch_kernel<R, 1, PIPE, RG, LDS>), dim3(grid), dim3(256), lds, s, tab); break;
-        case 2: hipLaunchKernelGGL((batch_tmarch_kernel<R, 2, PIPE, RG, LDS>), dim3(grid), dim3(256), lds, s, tab); break;
-        default: hipLaunchKernelGGL((batch_tmarch_kernel<R, 3, PIPE, RG, LDS>), dim3(grid), dim3(256), lds, s, tab); break;
+    if constexpr (LDS) {
+        switch (mode) {
+            case 0: hipLaunchKernelGGL((batch_tmarch_lds_kernel<R, 0>), dim3(grid), dim3(256), lds, s, tab); break;
+            case 1: hipLaunchKernelGGL((batch_tmarch_lds_kernel<R, 1>), dim3(grid), dim3(256), lds, s, tab); break;
+            case 2: hipLaunchKernelGGL((batch_tmarch_lds_kernel<R, 2>), dim3(grid), dim3(256), lds, s, tab); break;
+            default: hipLaunchKernelGGL((batch_tmarch_lds_kernel<R, 3>), dim3(grid), dim3(256), lds, s, tab); break;
+        }
+    } else {
+        switch (mode) {
+            case 0: hipLaunchKernelGGL((batch_tmarch_kernel<R, 0, PIPE, RG, false>), dim3(grid), dim3(256), 0, s, tab); break;
+            case 1: hipLaunchKernelGGL((batch_tmarch_kernel<R, 1, PIPE, RG, false>), dim3(grid), dim3(256), 0, s, tab); break;
+            case 2: hipLaunchKernelGGL((batch_tmarch_kernel<R, 2, PIPE, RG, false>), dim3(grid), dim3(256), 0, s, tab); break;
+            default: hipLaunchKernelGGL((batch_tmarch_kernel<R, 3, PIPE, RG, false>), dim3(grid), dim3(256), 0, s, tab); break;
+        }
     }
     return hipGetLastError();
 }
