@@ -484,7 +484,12 @@ __device__ __forceinline__ bool tmarch_block(const BatchHopTable<R>& tasks, int&
 constexpr int kTmLinkAux = 0;
 // Staged links keep the default policy too: the workgroups of a tile for the
 // other right-hand-side groups load the same links at about the same time.
-constexpr int kTmStageAux = 0;
+#ifndef TMH_TM_LDS_RHS_OUTER
+#define TMH_TM_LDS_RHS_OUTER 1
+#endif
+// (with the groups outermost each group fetches the links once, and they
+// pass L2 with the non-temporal hint)
+constexpr int kTmStageAux = TMH_TM_LDS_RHS_OUTER ? TMH_LINK_POLICY : 0;
 
 // The link of term TT of one step for this thread's pair, into registers.
 template <typename R, int TT>
@@ -544,8 +549,21 @@ __device__ __forceinline__ void tmarch_body(const BatchHopTable<R>& tasks) {
     if (!tmarch_block(tasks, ti, local)) return;
     const BatchHopTask<R>& T = tasks.t[ti];
     const int ngr = (T.nrhs + RG - 1) / RG;
-    const int rgi = local % ngr, tmp = local / ngr;
-    const int w = tmp % T.tm_nw, range = tmp / T.tm_nw;
+    int rgi, w, range;
+    if constexpr (LDS && TMH_TM_LDS_RHS_OUTER) {
+        // right-hand-side groups outermost: an XCD's resident workgroups
+        // cover a thicker block of the lattice for one group at a time
+        const int nranges = T.g.L[0] / T.tm_steps;
+        w = local % T.tm_nw;
+        const int tmp = local / T.tm_nw;
+        range = tmp % nranges;
+        rgi = tmp / nranges;
+    } else {
+        rgi = local % ngr;
+        const int tmp = local / ngr;
+        w = tmp % T.tm_nw;
+        range = tmp / T.tm_nw;
+    }
     // the same for a whole wave (kPairs is a multiple of 64): kept in an SGPR
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kPairs);
     const int rhs = rgi * RG + wave;
