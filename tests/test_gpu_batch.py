@@ -291,3 +291,39 @@ def test_batch_cg_tmarch_shapes(shape, use_graph):
                                           THETA_AP, 1e-10, 2000)
                 assert ok1 and abs(it1 - it[k]) <= 2
             k += 1
+
+
+@pytest.mark.slow
+def test_hop_mrhs_full_size_32x32x32x64():
+    """The benchmark lattice with 12 right-hand sides, in the shapes the
+    batched CG and the autotuner pick there (the LDS-staged t-march in FP64
+    and FP32, the pipelined t-march): every boundary time-slice and 5,000
+    random sites of 3 of the right-hand sides against the oracle, and all
+    sites and right-hand sides against the one-site-per-lane shape."""
+    dims, kappa, nrhs = (64, 32, 32, 32), 0.1632, 12
+    U = haar(dims, 951)
+    lat = tm.Lattice(dims)
+    Vh = lat.Vh
+    psis = [gauss(Vh, 960 + r) for r in range(nrhs)]
+    g = np.random.default_rng(97)
+    slab = dims[1] * dims[2] * dims[3] // 2
+    sites = np.unique(np.concatenate([np.arange(slab), np.arange(Vh - slab, Vh), g.integers(0, Vh, 5000)]))
+    for prec, tol, same in ((tm.F64, 1e-13, 1e-14), (tm.F32, 1e-5, 1e-6)):
+        G = tm.gauge_import(lat, U, prec)
+        inp = import_many(lat, psis, prec)
+        base = lat.new_spinors(nrhs, prec)
+        tm.hop_apply_mrhs(lat, "eo", base, G, inp, kappa, THETA_AP, prec, "256x1")
+        for shape in ("64x4/tmarch-lds", "256x1/tmarch-pipe"):
+            out = lat.new_spinors(nrhs, prec)
+            tm.hop_apply_mrhs(lat, "eo", out, G, inp, kappa, THETA_AP, prec, shape)
+            for r in (0, 5, 11):
+                src = psis[r] if prec == tm.F64 else round_f32(psis[r])
+                ref = oracle.hop_sites(dims, "eo", sites, U if prec == tm.F64 else round_f32(U), src, kappa,
+                                       THETA_AP)
+                got = host(tm.spinor_export(lat, out[r], prec))
+                assert site_rel_err(got[sites], ref) <= tol, (prec, shape, r)
+            for r in range(nrhs):
+                assert site_rel_err(host(tm.spinor_export(lat, out[r], prec)),
+                                    host(tm.spinor_export(lat, base[r], prec))) <= same, (prec, shape, r)
+            del out
+        del G, inp, base
