@@ -327,3 +327,30 @@ def test_hop_mrhs_full_size_32x32x32x64():
                                     host(tm.spinor_export(lat, base[r], prec))) <= same, (prec, shape, r)
             del out
         del G, inp, base
+
+
+@pytest.mark.slow
+def test_batch_cg_full_size_32x32x32x64():
+    """The batched CG with 12 right-hand sides on the benchmark lattice, on
+    the LDS-staged t-march shape the batch workload picks: every system
+    converges to 1e-10 by the solver's own FP64 true residual, two of them
+    are certified by the oracle's operator, and they agree with the
+    single-system CG."""
+    dims, kappa, nrhs = (64, 32, 32, 32), 0.1632, 12
+    mu = mu_of(kappa, 0.0013)
+    U = haar(dims, 971)
+    lat = tm.Lattice(dims)
+    bs = [gauss(lat.Vh, 980 + r) for r in range(nrhs)]
+    G = tm.gauge_import(lat, U)
+    m = dict(lat=lat, x=lat.new_spinors(nrhs), b=import_many(lat, bs), gauge=G, kappa=kappa, mu=mu, theta=THETA_AP)
+    it, res, ok = tm.batch_cg_solve([m], 1e-10, 2000, "64x4/tmarch-lds", True)
+    assert ok and max(res) <= 1e-10
+    for r in (0, 7):
+        x = host(tm.spinor_export(lat, m["x"][r]))
+        rr = bs[r] - oracle.normal(dims, U, x, kappa, mu, THETA_AP)
+        assert np.linalg.norm(rr) / np.linalg.norm(bs[r]) <= 1.05e-10, r
+    x1 = lat.new_spinor()
+    it1, _, ok1 = tm.cg_solve(lat, x1, m["b"][3].contiguous(), G, kappa, mu, THETA_AP, 1e-10, 2000)
+    assert ok1 and abs(it1 - it[3]) <= 2
+    d = host(tm.spinor_export(lat, x1)) - host(tm.spinor_export(lat, m["x"][3]))
+    assert np.linalg.norm(d) / np.linalg.norm(host(tm.spinor_export(lat, x1))) <= 1e-8
