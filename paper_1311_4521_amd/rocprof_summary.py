@@ -25,6 +25,16 @@ requests: no scale factor, and the streaming copy of known size in the same
 run checks them.  It writes a per-kernel table (bytes per launch and per
 site).
 
+    python -m paper_1311_4521_amd.rocprof_summary units OUT_MD DIR [DIR ...]
+
+``units`` reads counter runs that each include ``GRBM_GUI_ACTIVE`` and, per
+kernel, averages every other counter divided by the ``GRBM_GUI_ACTIVE`` of
+the same dispatch (busy and stall cycles of the texture-address, texture-data
+and L1 units, wave and instruction levels of the sequencers), leaving out
+dispatches shorter than a quarter of the kernel's longest (the early exits of
+iterations past convergence).  The streaming copy of the same run gives the
+reference row.
+
     python -m paper_1311_4521_amd.rocprof_summary gaps TRACE_CSV PATTERN [LAST_N]
 
 ``gaps`` measures, from a kernel trace, how much of the wall time of the
@@ -211,6 +221,47 @@ def requests(read_dir, write_dir, out_md, sites, copy_bytes, command=""):
     return res
 
 
+def units(out_md, dirs, command=""):
+    """Per kernel, the mean over its dispatches of counter / GRBM_GUI_ACTIVE
+    (see module docstring).  Returns {kernel: {counter: (mean, dispatches)}}."""
+    ratios = {}
+    for d in dirs:
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        for f in files:
+            disp = {}
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    e = disp.setdefault(r["Dispatch_Id"], {"": r["Kernel_Name"]})
+                    e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            longest = {}
+            for e in disp.values():
+                longest[e[""]] = max(longest.get(e[""], 0.0), e.get("GRBM_GUI_ACTIVE", 0.0))
+            for e in disp.values():
+                g = e.get("GRBM_GUI_ACTIVE", 0.0)
+                if g <= 0.0 or g < 0.25 * longest[e[""]]:
+                    continue
+                for c, v in e.items():
+                    if c not in ("", "GRBM_GUI_ACTIVE"):
+                        ratios.setdefault(e[""], {}).setdefault(c, []).append(v / g)
+    res = {k: {c: (sum(v) / len(v), len(v)) for c, v in cs.items()} for k, cs in ratios.items()
+           if "tmh::" in k or COPY in k}
+    counters = sorted({c for cs in res.values() for c in cs})
+    lines = ["Each entry: counter / GRBM_GUI_ACTIVE of the same dispatch, averaged over the kernel's "
+             "dispatches (early exits left out).", "",
+             "| kernel | " + " | ".join(f"`{c}`" for c in counters) + " |",
+             "|---|" + "---|" * len(counters)]
+    for k in sorted(res, key=lambda k: (COPY not in k, short_name(k, 90))):
+        cells = [f"{res[k][c][0]:.4g}" if c in res[k] else "" for c in counters]
+        lines.append(f"| `{short_name(k, 90)}` | " + " | ".join(cells) + " |")
+    with open(out_md, "w") as fh:
+        if command:
+            fh.write(command.rstrip() + "\n\n")
+        fh.write("\n".join(lines) + "\n")
+    return res
+
+
 def gaps(trace_csv, pattern, last_n=None):
     """(kernel busy ns, wall ns, dispatches) over the last `last_n` dispatches
     whose names contain `pattern`, taken as one back-to-back stretch."""
@@ -240,6 +291,8 @@ if __name__ == "__main__":
     elif cmd == "requests":
         requests(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), float(sys.argv[6]),
                  command=os.environ.get("TMH_PROFILE_COMMAND", ""))
+    elif cmd == "units":
+        units(sys.argv[2], sys.argv[3:], command=os.environ.get("TMH_PROFILE_COMMAND", ""))
     elif cmd == "gaps":
         b, wl, n = gaps(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) > 4 else None)
         print(f"{n} dispatches: kernels busy {b / 1e6:.3f} ms of {wl / 1e6:.3f} ms wall, "

@@ -123,3 +123,27 @@ def test_short_name_keeps_template_arguments():
         "hop_kernel<half_t, 0, 1>"
     long = "void at::native::elementwise_kernel<" + "x" * 100 + ">(int)"
     assert rs.short_name(long, 40).endswith("...") and len(rs.short_name(long, 40)) == 40
+
+
+def test_units_divides_by_the_active_cycles_and_drops_early_exits(tmp_path):
+    d = tmp_path / "u"
+    d.mkdir()
+    rows = [  # (dispatch, kernel, counter, value)
+        (0, COPY, "GRBM_GUI_ACTIVE", 1000.0), (0, COPY, "TA_BUSY_avr", 800.0),
+        (1, DOM, "GRBM_GUI_ACTIVE", 2000.0), (1, DOM, "TA_BUSY_avr", 1000.0),
+        (2, DOM, "GRBM_GUI_ACTIVE", 4000.0), (2, DOM, "TA_BUSY_avr", 3000.0),
+        (3, DOM, "GRBM_GUI_ACTIVE", 100.0), (3, DOM, "TA_BUSY_avr", 100.0),  # early exit
+        (4, "other", "GRBM_GUI_ACTIVE", 10.0), (4, "other", "TA_BUSY_avr", 1.0),
+    ]
+    with open(d / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for k, name, c, v in rows:
+            w.writerow({"Dispatch_Id": k, "Kernel_Name": name, "Counter_Name": c, "Counter_Value": v})
+    out = tmp_path / "u.md"
+    res = rs.units(str(out), [str(d)], command="cmd")
+    assert res[COPY]["TA_BUSY_avr"] == (pytest.approx(0.8), 1)
+    assert res[DOM]["TA_BUSY_avr"] == (pytest.approx((0.5 + 0.75) / 2), 2)
+    assert "other" not in res
+    text = out.read_text()
+    assert text.startswith("cmd") and "`stream_copy_kernel" in text and "0.625" in text
