@@ -66,11 +66,13 @@ __device__ __forceinline__ int unit_site(int b, int w, int nb, int xgroup, int n
 }
 
 #ifndef TMH_HOP_PIPE_F16
-#define TMH_HOP_PIPE_F16 0
+#define TMH_HOP_PIPE_F16 2
 #endif
-// Software pipelining per storage precision.  FP16 runs without it: the
-// single register set (72 VGPRs, 7 waves per SIMD) was measured 4 % faster
-// at 32^3x64 than the pipelined one (117 VGPRs, 4 waves).
+// Software pipelining per storage precision.  FP16 (2) pipelines on the
+// storage words (hop_site_raw: 89-95 VGPRs, 5 waves per SIMD), 2.5-3.5 %
+// faster at 32^3x64 than one term at a time (66-76 VGPRs, 6-7 waves); the
+// pipelined form on widened values (1: 117 VGPRs, 4 waves) was 4 % slower
+// than one term at a time.
 template <typename P>
 constexpr bool kHopPipe = (sizeof(typename Word<P>::T) == 4 ? TMH_HOP_PIPE_F16 : TMH_HOP_PIPE) != 0;
 
@@ -104,7 +106,10 @@ __global__ void __launch_bounds__(kHopBlock) TMH_HOP_ATTR hop_kernel(HopArgs<P> 
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc[s][k] = mk<R>(0, 0);
         const SiteNb n = site_neighbours(a.g, c, lex);
-        hop_site<P, kHopPipe<P>, kLinkAux, LF>(acc, a, n, i);
+        if constexpr (sizeof(typename Word<P>::T) == 4 && TMH_HOP_PIPE_F16 == 2)
+            hop_site_raw<kLinkAux, LF>(acc, a, n, i);
+        else
+            hop_site<P, kHopPipe<P>, kLinkAux, LF>(acc, a, n, i);
         const int S = a.g.S;
         const R alpha = MODE >= 3 ? (R)a.scal[kAlpha] : (R)0;
 #pragma unroll

@@ -322,6 +322,64 @@ __device__ __forceinline__ void hop_site(cx<real_t<P>> (&acc)[4][3], const HopAr
     }
 }
 
+// FP16 storage, pipelined on the storage words: the loads of term t+1 stay in
+// flight while term t is computed, held as binary16 pairs (one register per
+// complex number, against two once widened), and each term is widened to
+// FP32 just before it is used.  The widening is exact, so the sum is the
+// same as the one-term-at-a-time form's.
+template <int LF> struct TermRaw {
+    h2 psi[12];
+    h2 u[link_comps<LF>()];
+};
+
+template <int T, int LAUX, int LF>
+__device__ __forceinline__ void load_t_raw(TermRaw<LF>& d, const HopArgs<half_t>& a, const SiteNb& n, int i) {
+    constexpr int MU = T / 2;
+    constexpr int NC = link_comps<LF>();
+    const int S = a.g.S;
+    const unsigned nb = (unsigned)S * sizeof(h2);
+    const h2* link = (T % 2 == 0 ? a.gout : a.gin) + (int64_t)MU * NC * S;
+    const unsigned jl = (unsigned)(T % 2 == 0 ? i : n.jn[T]) * sizeof(h2);
+    const unsigned jn = (unsigned)n.jn[T] * sizeof(h2);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) d.psi[k] = BufIO<half_t>::load<0>(buf_rsrc(a.in + (int64_t)k * S, nb), jn);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) d.u[k] = BufIO<half_t>::load<LAUX>(buf_rsrc(link + (int64_t)k * S, nb), jl);
+}
+
+template <int LF>
+__device__ __forceinline__ void widen_term(TermData<float>& d, const TermRaw<LF>& r) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) d.psi[k / 3][k % 3] = mk<float>((float)r.psi[k].x, (float)r.psi[k].y);
+#pragma unroll
+    for (int k = 0; k < link_comps<LF>(); ++k) d.u[k / 3][k % 3] = mk<float>((float)r.u[k].x, (float)r.u[k].y);
+}
+
+template <int LAUX, int LF>
+__device__ __forceinline__ void hop_site_raw(cx<float> (&acc)[4][3], const HopArgs<half_t>& a, const SiteNb& n,
+                                             int i) {
+    TermRaw<LF> r0, r1;
+    TermData<float> d;
+    load_t_raw<0, LAUX, LF>(r0, a, n, i);
+    TMH_SCHED_FENCE();
+    load_t_raw<1, LAUX, LF>(r1, a, n, i);
+    TMH_SCHED_FENCE();
+#define TMH_RAW_STEP(T, RT, RN)                       \
+    widen_term<LF>(d, RT);                            \
+    add_t<half_t, T, LF>(acc, d, a, n);               \
+    TMH_SCHED_FENCE();                                \
+    load_t_raw<T + 2, LAUX, LF>(RT, a, n, i);         \
+    TMH_SCHED_FENCE();
+    TMH_RAW_STEP(0, r0, r1) TMH_RAW_STEP(1, r1, r0) TMH_RAW_STEP(2, r0, r1) TMH_RAW_STEP(3, r1, r0)
+    TMH_RAW_STEP(4, r0, r1) TMH_RAW_STEP(5, r1, r0)
+#undef TMH_RAW_STEP
+    widen_term<LF>(d, r0);
+    add_t<half_t, 6, LF>(acc, d, a, n);
+    TMH_SCHED_FENCE();
+    widen_term<LF>(d, r1);
+    add_t<half_t, 7, LF>(acc, d, a, n);
+}
+
 // Multi-right-hand-side form: NR fields `fstride` words apart share every
 // link load.  Per term the link goes to registers once and is applied to the
 // NR neighbour spinors in turn; right-hand sides r >= nv are skipped.
